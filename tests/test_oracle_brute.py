@@ -1,0 +1,152 @@
+"""The oracle against the brute-force checker and against invariants.
+
+- On many tiny random netlists (several cycles, multi-edge inputs, wire
+  delays, conditional arcs, zero-delay mode) the event-queue oracle and the
+  independent gate-by-gate 1 ps-grid checker must give identical waveforms
+  and SAIF counts.
+- On larger seeded workloads the oracle must satisfy facts that follow from
+  the semantics: T0 + T1 equals the simulated time, each cycle starts from
+  the zero-delay settled values (computed here by a separate numpy
+  evaluation), the number of edges of a net over a range of cycles has the
+  parity of its settled-value change across the range, and edge lists are
+  strictly increasing and non-negative.
+- Cycle isolation: on a netlist that settles within every period the
+  per-cycle result equals one continuous run over all cycles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2203_06117_amd import synth
+
+
+def _tiny(seed, wires, cond, zero):
+    rng = np.random.default_rng(seed)
+    G = int(rng.integers(1, 11))
+    I = int(rng.integers(3, 5))
+    L = int(rng.integers(1, min(G, 4) + 1))
+    T = int(rng.integers(25, 45))
+    dlo, dhi = (0, 0) if zero else (1, int(rng.integers(1, 9)))
+    w = synth.small_random(seed, G, I, L, 3, T, 0.5, dlo, dhi, cond_frac=0.5 if cond else 0.0,
+                           wire=None if (zero or not wires) else (1, int(rng.integers(1, 7))),
+                           extra=2, extra_p=0.4, skew=T - 1)
+    return w
+
+
+@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero"])
+def test_oracle_matches_brute(mode):
+    n_ok = 0
+    for seed in range(1000, 1120):
+        w = _tiny(seed, "wires" in mode, "cond" in mode, mode == "zero")
+        tc, t0, t1, waves = brute.simulate(w)
+        N = len(tc)
+        C = w["stimulus"]["n_cycles"]
+        probes = [(n, c) for n in range(N) for c in range(C)]
+        r = oracle.simulate(w, probes=probes)
+        assert r["tc"].tolist() == tc, seed
+        assert r["t0"].tolist() == t0, seed
+        assert r["t1"].tolist() == t1, seed
+        for (n, c), (pinit, ptimes, _) in zip(probes, r["probes"]):
+            assert (pinit, ptimes) == waves[(n, c)], (seed, n, c)
+        n_ok += 1
+    assert n_ok == 120
+
+
+def _levels_numpy(net):
+    I, G = net["n_inputs"], net["n_gates"]
+    fp, fn = net["fanin_ptr"], net["fanin_net"]
+    lvl = np.full(I + G, -1, dtype=np.int64)
+    lvl[:I] = 0
+    slot_gate = np.repeat(np.arange(G), np.diff(fp))
+    for _ in range(G + 1):
+        src = lvl[fn]
+        ready = np.ones(G, dtype=bool)
+        np.logical_and.at(ready, slot_gate, src >= 0)
+        mx = np.zeros(G, dtype=np.int64)
+        np.maximum.at(mx, slot_gate, src)
+        new = np.where(ready, mx + 1, -1)
+        if np.array_equal(new, lvl[I:]):
+            break
+        lvl[I:] = new
+    return lvl
+
+
+def _settle_numpy(net, input_vals):
+    """Zero-delay values of every net for the given input values."""
+    I, G = net["n_inputs"], net["n_gates"]
+    fp, fn = net["fanin_ptr"], net["fanin_net"]
+    truth = net["cell_truth"][net["cell_of_gate"]].astype(np.uint64)
+    lvl = _levels_numpy(net)
+    val = np.zeros(I + G, dtype=np.int64)
+    val[:I] = input_vals
+    k = np.diff(fp)
+    for L in range(1, lvl.max() + 1):
+        gs = np.nonzero(lvl[I:] == L)[0]
+        idx = np.zeros(len(gs), dtype=np.int64)
+        for j in range(int(k.max())):
+            has = k[gs] > j
+            idx[has] |= val[fn[fp[gs[has]] + j]] << j
+        val[I + gs] = ((truth[gs] >> idx.astype(np.uint64)) & np.uint64(1)).astype(np.int64)
+    return val
+
+
+def _inputs_at(stim, t_abs):
+    tp, ts = stim["toggle_ptr"], stim["toggle_ps"]
+    I = len(stim["init"])
+    before = np.array([np.searchsorted(ts[tp[i]:tp[i + 1]], t_abs, side="left") for i in range(I)])
+    return (stim["init"].astype(np.int64) + before) & 1
+
+
+@pytest.mark.parametrize("which", ["tiny", "cond-wires"])
+def test_oracle_invariants(which):
+    if which == "tiny":
+        w = synth.tiny()
+    else:
+        w = synth.small_random(77, 3000, 80, 30, 40, 600, 0.3, 3, 40, cond_frac=0.2, wire=(1, 6),
+                               extra=1, extra_p=0.2)
+    net, stim = w["netlist"], w["stimulus"]
+    C, T = stim["n_cycles"], stim["period"]
+    b, e = 7, C - 3
+    N = net["n_inputs"] + net["n_gates"]
+    rng = np.random.default_rng(3)
+    sample = [(int(n), int(c)) for n, c in zip(rng.integers(0, N, 300), rng.integers(b, e, 300))]
+    r = oracle.simulate(w, b, e, probes=sample)
+    assert np.all(r["t0"] + r["t1"] == (e - b) * T)
+    s_b = _settle_numpy(net, _inputs_at(stim, b * T))
+    s_e = _settle_numpy(net, _inputs_at(stim, e * T))
+    assert np.array_equal(r["tc"] % 2, s_b ^ s_e)
+    for (n, c), (init, times, ln) in zip(sample, r["probes"]):
+        s_c = _settle_numpy(net, _inputs_at(stim, c * T))
+        assert init == s_c[n]
+        assert all(x >= 0 for x in times)
+        assert all(x < y for x, y in zip(times, times[1:]))
+        s_n = _settle_numpy(net, _inputs_at(stim, (c + 1) * T))
+        assert (init ^ (ln & 1)) == s_n[n]
+
+
+def test_cycle_isolation_matches_continuous_run():
+    """Delays 5..20 over 24 levels settle well inside a 1000 ps period, so
+    simulating every cycle on its own equals one continuous run."""
+    net = synth.make_netlist(11, 2000, 64, 24)
+    arcs = synth.make_arcs(11, net, 5, 20, 0.1)
+    C, T = 30, 1000
+    stim = synth.make_stimulus(11, 64, C, T, 0.3, skew=50)
+    w = {"netlist": net, "arcs": arcs, "wires": None, "stimulus": stim}
+    per_cycle = oracle.simulate(w)
+    cont_stim = dict(stim, period=C * T, n_cycles=1)
+    N = 64 + 2000
+    probes_c = [(n, 0) for n in range(0, N, 37)]
+    cont = oracle.Oracle(net, arcs).run(cont_stim, 0, 1, probes=probes_c)
+    assert np.array_equal(per_cycle["tc"], cont["tc"])
+    assert np.array_equal(per_cycle["t1"], cont["t1"])
+    assert np.array_equal(per_cycle["t0"], cont["t0"])
+    probes_s = [(n, c) for n in range(0, N, 37) for c in range(C)]
+    r = oracle.simulate(w, probes=probes_s)
+    for i, n in enumerate(range(0, N, 37)):
+        joined = []
+        for c in range(C):
+            init, times, _ = r["probes"][i * C + c]
+            joined += [c * T + x for x in times]
+            assert all(x < T for x in times)
+        assert joined == cont["probes"][i][1]

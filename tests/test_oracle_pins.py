@@ -1,0 +1,230 @@
+"""Pins for the oracle: closed forms, textbook functions and hand derivations.
+
+Each test fixes the oracle to something other than itself: the Boolean
+functions of the cell types, the arithmetic of delay chains, the closed form
+of the inertial pulse filter, and small circuits worked out by hand from the
+rules of GATSPI's Algorithm 1 (Section 3).
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.handmade import work
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+TEXTBOOK = {
+    "INV": lambda a: 1 - a,
+    "BUF": lambda a: a,
+    "NAND2": lambda a, b: 1 - (a & b),
+    "NOR2": lambda a, b: 1 - (a | b),
+    "AND3": lambda a, b, c: a & b & c,
+    "XOR2": lambda a, b: a ^ b,
+    "AOI21": lambda a1, a2, b: 1 - ((a1 & a2) | b),
+    "MUX2": lambda i0, i1, s: i1 if s else i0,
+}
+
+
+def run1(w, probes):
+    return oracle.simulate(w, probes=probes)
+
+
+@pytest.mark.parametrize("cell", list(TEXTBOOK))
+def test_truth_tables_zero_delay(cell):
+    """Every cell, every input vector, every pin toggling: zero-delay mode
+    gives the textbook function before and after the toggle, one edge iff it
+    changes, at the toggle time."""
+    f = TEXTBOOK[cell]
+    k = f.__code__.co_argcount
+    for x in range(1 << k):
+        for j in range(k):
+            bits = [(x >> i) & 1 for i in range(k)]
+            tog = [[5] if i == j else [] for i in range(k)]
+            w = work(k, [(cell, list(range(k)))], (0, 0), tog, bits, period=100)
+            r = run1(w, [(k, 0)])
+            init, times, n = r["probes"][0]
+            before = f(*bits)
+            after_bits = list(bits)
+            after_bits[j] ^= 1
+            after = f(*after_bits)
+            assert init == before, (cell, bits, j)
+            assert times == ([5] if after != before else []), (cell, bits, j)
+
+
+def test_inv_buf_chains():
+    """Single edges through INV/BUF chains arrive after the summed stage
+    delays, each stage using its rise or fall delay by the edge it makes."""
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        n = int(rng.integers(1, 9))
+        cells = [("INV" if rng.integers(2) else "BUF") for _ in range(n)]
+        rise = rng.integers(1, 40, size=n).tolist()
+        fall = rng.integers(1, 40, size=n).tolist()
+        gates = [(c, [i]) for i, c in enumerate(cells)]
+        arcs = [(i, 0, -1, 0, rise[i], fall[i]) for i in range(n)]
+        period, C = 1000, 6
+        init = int(rng.integers(2))
+        tog = sorted(set(int(c * period + rng.integers(0, 200)) for c in range(C) if rng.integers(3)))
+        w = work(1, gates, arcs, [tog], [init], period=period, n_cycles=C)
+        probes = [(1 + i, c) for i in range(n) for c in range(C)]
+        r = run1(w, probes)
+        for c in range(C):
+            v = (init + sum(1 for t in tog if t < c * period)) & 1
+            edges = [t - c * period for t in tog if c * period <= t < (c + 1) * period]
+            for i in range(n):
+                out_v = v if cells[i] == "BUF" else 1 - v
+                out_edges = []
+                val = out_v
+                for t in edges:
+                    val ^= 1
+                    out_edges.append(t + (rise[i] if val else fall[i]))
+                pi = probes.index((1 + i, c))
+                assert r["probes"][pi][0] == out_v
+                assert r["probes"][pi][1] == out_edges, (trial, c, i)
+                v, edges = out_v, out_edges
+
+
+def _pulse_grid(cell, init):
+    """One gate per (leading delay, trailing delay, width); returns the
+    workload and the case list."""
+    cases = [(dl, dt, wdt) for dl in range(1, 13) for dt in range(1, 13) for wdt in range(1, 15)]
+    gates, arcs, tog = [], [], []
+    n = len(cases)
+    for g, (dl, dt, wdt) in enumerate(cases):
+        gates.append((cell, [g]))
+        out_rises_first = (init == 0) == (cell == "BUF")
+        rise, fall = (dl, dt) if out_rises_first else (dt, dl)
+        arcs.append((g, 0, -1, 0, rise, fall))
+        tog.append([10, 10 + wdt])
+    return work(n, gates, arcs, tog, [init] * n, period=100), cases
+
+
+@pytest.mark.parametrize("cell", ["BUF", "INV"])
+@pytest.mark.parametrize("init", [0, 1])
+def test_gate_pulse_closed_form(cell, init):
+    """A pulse of width w through a gate with leading-edge delay d_l and
+    trailing-edge delay d_t survives iff w >= d_l and then has width
+    w + d_t - d_l, starting at a + d_l."""
+    w, cases = _pulse_grid(cell, init)
+    n = len(cases)
+    r = run1(w, [(n + g, 0) for g in range(n)])
+    for g, (dl, dt, wdt) in enumerate(cases):
+        _, times, _ = r["probes"][g]
+        if wdt >= dl:
+            assert times == [10 + dl, 10 + wdt + dt], (cell, init, dl, dt, wdt)
+        else:
+            assert times == [], (cell, init, dl, dt, wdt)
+
+
+@pytest.mark.parametrize("init", [0, 1])
+def test_wire_pulse_closed_form(init):
+    """The interconnect filter obeys the same closed form with the wire's
+    rise/fall delays; a BUF with unit delays behind it shifts the result by 1."""
+    cases = [(dl, dt, wdt) for dl in range(1, 11) for dt in range(1, 11) for wdt in range(1, 13)]
+    n = len(cases)
+    gates = [("BUF", [g]) for g in range(n)]
+    wires = []
+    for dl, dt, wdt in cases:
+        wires.append((dl, dt) if init == 0 else (dt, dl))
+    w = work(n, gates, (1, 1), [[10, 10 + c[2]] for c in cases], [init] * n, period=100, wires=wires)
+    r = run1(w, [(n + g, 0) for g in range(n)])
+    for g, (dl, dt, wdt) in enumerate(cases):
+        _, times, _ = r["probes"][g]
+        if wdt >= dl:
+            assert times == [11 + dl, 11 + wdt + dt]
+        else:
+            assert times == []
+
+
+def test_xor_glitch_generator():
+    """One net through two buffers of delays a and b into an XOR2: a pulse
+    of width |a-b| appears, filtered iff |a-b| is below the XOR's rise delay;
+    equal delays switch both pins at once and give no edge."""
+    for a, b, rx, fx in itertools.product(range(1, 7), range(1, 7), range(1, 6), range(1, 6)):
+        gates = [("BUF", [0]), ("BUF", [0]), ("XOR2", [1, 2])]
+        arcs = [(0, 0, -1, 0, a, a), (1, 0, -1, 0, b, b),
+                (2, 0, -1, 0, rx, fx), (2, 1, -1, 0, rx, fx)]
+        w = work(1, gates, arcs, [[10]], [0], period=100)
+        _, times, _ = run1(w, [(3, 0)])["probes"][0]
+        lo, hi = min(a, b), max(a, b)
+        if a == b or hi - lo < rx:
+            assert times == [], (a, b, rx, fx)
+        else:
+            assert times == [10 + lo + rx, 10 + hi + fx], (a, b, rx, fx)
+
+
+def test_msi_min_delay():
+    """Several pins switching at one time: the output edge takes the
+    smallest of their arc delays (here the last pin in index order has the
+    larger delay, so reading it literally would differ)."""
+    for fa, fb in [(3, 7), (7, 3), (5, 5)]:
+        arcs = [(0, 0, -1, 0, 20, fa), (0, 1, -1, 0, 20, fb)]
+        w = work(2, [("NAND2", [0, 1])], arcs, [[10], [10]], [0, 0], period=100)
+        init, times, _ = run1(w, [(2, 0)])["probes"][0]
+        assert init == 1 and times == [10 + min(fa, fb)]
+    # AND3 with its third pin held at 1
+    arcs = [(0, 0, -1, 0, 9, 1), (0, 1, -1, 0, 4, 1), (0, 2, -1, 0, 2, 1)]
+    w = work(3, [("AND3", [0, 1, 2])], arcs, [[10], [10], []], [0, 0, 1], period=100)
+    assert run1(w, [(3, 0)])["probes"][0][:2] == (0, [14])
+    # XOR2 with both pins switching together: no edge at all
+    w = work(2, [("XOR2", [0, 1])], (3, 3), [[10], [10]], [0, 1], period=100)
+    assert run1(w, [(2, 0)])["probes"][0][:2] == (1, [])
+
+
+def test_conditional_delays():
+    """SDF-style conditional arcs: pin A's delay depends on side pin B's
+    value; B unconditional.  Cycles: A rises with B=0, A falls with B=0,
+    B rises, A rises with B=1, A falls with B=1."""
+    r0, f0, r1, f1, rb, fb = 11, 13, 17, 19, 5, 7
+    arcs = [(0, 0, 1, 0, r0, f0), (0, 0, 1, 1, r1, f1), (0, 1, -1, 0, rb, fb)]
+    T = 100
+    togA = [10, 110, 310, 410]
+    togB = [210]
+    w = work(2, [("XOR2", [0, 1])], arcs, [togA, togB], [0, 0], period=T, n_cycles=5)
+    r = run1(w, [(2, c) for c in range(5)])
+    got = [p[:2] for p in r["probes"]]
+    assert got == [(0, [10 + r0]),          # A 0->1, B=0: XOR rises, r0
+                   (1, [10 + f0]),          # A 1->0, B=0: XOR falls, f0
+                   (0, [10 + rb]),          # B 0->1: XOR rises via B
+                   (1, [10 + f1]),          # A 0->1, B=1: XOR falls, f1
+                   (0, [10 + r1])]          # A 1->0, B=1: XOR rises, r1
+
+
+def test_conditional_uses_state_after_switching():
+    """When the condition pin switches together with the arc's pin, the
+    condition is read in the pin state after both switched."""
+    # NAND2: pin 0 fall delay 30 when pin1 = 0, 4 when pin1 = 1; pin 1 fall 9
+    arcs = [(0, 0, 1, 0, 50, 30), (0, 0, 1, 1, 50, 4), (0, 1, -1, 0, 50, 9)]
+    w = work(2, [("NAND2", [0, 1])], arcs, [[10], [10]], [0, 0], period=100)
+    assert run1(w, [(2, 0)])["probes"][0][:2] == (1, [14])
+
+
+def test_cycles_are_isolated():
+    """Each cycle starts from the settled values; an edge later than the
+    period still belongs to its cycle and is clipped out of T0/T1."""
+    w = work(1, [("BUF", [0])], (150, 150), [[20]], [0], period=100, n_cycles=2)
+    r = run1(w, [(1, 0), (1, 1)])
+    assert r["probes"][0][:2] == (0, [170])
+    assert r["probes"][1][:2] == (1, [])
+    assert r["tc"].tolist() == [1, 1]
+    assert r["t1"].tolist() == [80 + 100, 0 + 100]
+    assert r["t0"].tolist() == [20, 100]
+
+
+@pytest.mark.parametrize("path", sorted(f for f in os.listdir(GOLDEN) if f.endswith(".json")))
+def test_golden_fixture(path):
+    """Hand-derived waveforms stored under tests/golden (each file states its
+    derivation and the passage it follows)."""
+    with open(os.path.join(GOLDEN, path)) as fh:
+        fx = json.load(fh)
+    wires = [tuple(x) for x in fx["wires"]] if fx.get("wires") else None
+    w = work(fx["n_inputs"], [tuple(g) for g in fx["gates"]], [tuple(a) for a in fx["arcs"]],
+             fx["toggles"], fx["init"], period=fx["period"], n_cycles=fx["n_cycles"], wires=wires)
+    probes = [(e["net"], e["cycle"]) for e in fx["expect"]]
+    r = run1(w, probes)
+    for e, p in zip(fx["expect"], r["probes"]):
+        assert (p[0], p[1]) == (e["init"], e["times"]), e
