@@ -1,0 +1,286 @@
+/*
+ * gatesim.h — C ABI of the MI355X (gfx950) gate-level re-simulator.
+ *
+ * The library re-simulates combinational gate-level netlists whose input
+ * waveforms (primary inputs and register/RAM outputs) are known, with
+ * per-arc rise/fall gate delays, SDF-style conditional delays, optional
+ * interconnect delays and inertial pulse filtering, and reduces the result
+ * to SAIF-style per-net toggle counts and time-at-0/1.  This is the method
+ * of GATSPI (Zhang, Ren, Sridharan, Khailany, DAC 2022): re-simulation with
+ * the cycle-to-cycle dependency broken by the known sequential waveforms
+ * (Section 1), levelized evaluation with every gate of a level and every
+ * cycle simulated in parallel (Section 3), and the per-gate, per-cycle
+ * waveform algorithm of Algorithm 1.
+ *
+ * Conventions for every call:
+ *  - Every function returns a gs_status; nothing throws or aborts across
+ *    the ABI.  On failure gs_last_error() describes the cause.
+ *  - Input arrays are host pointers, borrowed for the duration of the call
+ *    only (copied or uploaded before return).  Output arrays are host
+ *    pointers owned by the caller.
+ *  - Device memory belongs to the context, or to the caller's arena when
+ *    gs_options.arena is set (the caller keeps it alive until gs_destroy).
+ *  - All times are integer picoseconds; counts and SAIF sums are int64.
+ *  - A context is used by one host thread at a time, except gs_submit,
+ *    gs_poll and gs_release, which are thread-safe.
+ *
+ * Semantics (the "cycle-isolated" model of re-simulation; GATSPI Section 1
+ * and Section 3, Algorithm 1):
+ *  - Cycle c covers absolute times [c*T, (c+1)*T) and is simulated on its
+ *    own in local time t = absolute - c*T.  At t = 0 each input holds its
+ *    value from just before c*T and every net holds the zero-delay settled
+ *    value (Algorithm 1, initial value).  The cycle runs to quiescence;
+ *    edges later than T count toward the cycle's TC but T0/T1 only measure
+ *    [0, T).
+ *  - Interconnect filter (Algorithm 1, net-delay filtering): a net pulse
+ *    narrower than the wire delay of its leading edge never reaches the pin.
+ *  - Multiple simultaneous inputs (Algorithm 1, MSI resolution): pins
+ *    switching at the same time are applied together; the output edge takes
+ *    the smallest of their arc delays, looked up in the pin state after the
+ *    switch.
+ *  - Gate inertial filter with PATHPULSEPERCENT = 100 (Algorithm 1, output
+ *    filter): when the output must change while its previous edge is still
+ *    pending, the pending edge is cancelled; otherwise a new edge is
+ *    scheduled after the arc delay.
+ *  - SAIF (Section 3): TC = edges of the net, T1/T0 = time at 1/0, summed
+ *    over the simulated cycles.
+ */
+#ifndef GATESIM_H
+#define GATESIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gs_status;
+#define GS_OK           0
+#define GS_E_INVALID   -1   /* malformed argument or input data */
+#define GS_E_NOT_DAG   -2   /* the netlist has a combinational cycle */
+#define GS_E_NOMEM     -3   /* the memory budget cannot hold one tile of one window */
+#define GS_E_DEVICE    -4   /* a HIP runtime call failed or no GPU is present */
+#define GS_E_STATE     -5   /* call out of order (e.g. simulate before arcs) */
+#define GS_E_BUSY      -6   /* serving admission queue is full */
+#define GS_E_CAPACITY  -7   /* more than 65535 transitions in one net's 64-cycle tile */
+
+typedef struct gs_ctx gs_ctx;
+
+/* Level schedules of the gate-evaluation kernel. */
+#define GS_SCHED_LEVELS 0   /* one launch per logic level (GATSPI's level partition, Section 3) */
+#define GS_SCHED_GRAPH  1   /* the same launches captured once into a HIP graph and replayed per window */
+
+typedef struct {
+    int32_t  device;          /* HIP device ordinal */
+    void    *stream;          /* hipStream_t to run on, borrowed (e.g. torch's current stream); NULL = own stream */
+    uint64_t hbm_budget;      /* bytes of device memory the context may hold for waveforms; 0 = 80% of free memory */
+    void    *arena;           /* optional caller-owned device buffer used for all waveform storage */
+    uint64_t arena_bytes;
+    int32_t  window_cycles;   /* cycles per window; 0 = as many as fit the budget, capped at 4096 */
+    int32_t  lds_cap;         /* transitions per (net, cycle) staged on chip before the spill path: 4, 8, 16 or 32; 0 = 16 */
+    int32_t  waves_per_block; /* 1, 2, 4 or 8; 0 = 4 */
+    int32_t  schedule;        /* GS_SCHED_LEVELS or GS_SCHED_GRAPH */
+    int32_t  timing;          /* nonzero: time every gate-evaluation launch with HIP events (gs_get_stats) */
+    int32_t  reserved[7];
+} gs_options;
+
+/* Fills *opt with the defaults above. */
+void gs_default_options(gs_options *opt);
+
+/* Creates a context on opt->device (opt may be NULL for defaults).
+ * Errors: GS_E_DEVICE if the device cannot be used, GS_E_INVALID. */
+gs_status gs_create(const gs_options *opt, gs_ctx **out);
+gs_status gs_destroy(gs_ctx *ctx);
+
+/* Message for the last failure of ctx, or of a context-free call on this
+ * thread when ctx is NULL.  Valid until the next call on the same ctx. */
+const char *gs_last_error(gs_ctx *ctx);
+
+/* Cell library (Algorithm 1's truth table Y[2^n]): cell c has n_pins[c]
+ * inputs (1..6) and output bit b of truth[c] for input index b, pin 0 being
+ * the least significant bit of b.  Replaces any previous library; designs
+ * loaded earlier keep theirs. */
+gs_status gs_load_cells(gs_ctx *ctx, int32_t n_cells, const uint8_t *n_pins, const uint64_t *truth);
+
+/* Netlist (Section 3: the gate-level netlist as a graph).  Nets 0..n_inputs-1
+ * are inputs; gate g drives net n_inputs + g.  Gate g's pins are
+ * fanin_net[fanin_ptr[g] .. fanin_ptr[g+1]) in pin order; their number must
+ * equal the cell's pin count and a gate's fanin nets may repeat.  The
+ * netlist is levelized on the GPU (level 0 = inputs, a gate's level = 1 +
+ * the largest fanin level).  Errors: GS_E_INVALID (ids out of range, arity
+ * mismatch), GS_E_NOT_DAG.  *design_id receives the new design's id. */
+gs_status gs_load_netlist(gs_ctx *ctx, int32_t n_inputs, int32_t n_gates, const int32_t *cell_of_gate,
+                          const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t *design_id);
+
+/* One SDF-style delay arc (Algorithm 1's per-pin gate delay table, Section 3
+ * on conditional delay statements): the delay from pin `pin` of `gate` to
+ * the output for a rising (rise_ps) and a falling (fall_ps) output edge.
+ * cond_pin < 0: unconditional.  cond_pin >= 0: applies only while pin
+ * cond_pin of the same gate has value cond_val, and then takes precedence
+ * over the unconditional record.  16 bytes, natural alignment. */
+typedef struct {
+    int32_t gate;
+    int8_t  pin;
+    int8_t  cond_pin;
+    int8_t  cond_val;
+    int8_t  reserved;
+    int32_t rise_ps;
+    int32_t fall_ps;
+} gs_arc;
+
+/* Delay arcs of a design.  For every (gate, pin, state of the other pins)
+ * exactly one record must apply after precedence; all conditional records
+ * of one (gate, pin) must key on the same condition pin.  Delays are either
+ * all >= 1, or all 0 together with all wire delays (zero-delay mode).
+ * Replaces earlier arcs of the design.  Errors: GS_E_INVALID. */
+gs_status gs_load_arcs(gs_ctx *ctx, int32_t design, int64_t n_arcs, const gs_arc *arcs);
+
+/* Interconnect delays (Algorithm 1's per-pin wire delays), one rise/fall
+ * pair per fanin slot in CSR order; NULL pointers mean all zero.  Each pair
+ * is both 0 or both >= 1.  Errors: GS_E_INVALID. */
+gs_status gs_load_wires(gs_ctx *ctx, int32_t design, const int32_t *rise_ps, const int32_t *fall_ps);
+
+/* Input waveforms (the known primary/pseudo-primary waveforms of
+ * re-simulation, Section 1): input i starts at init[i] (0/1) and toggles at
+ * the absolute times toggle_ps[toggle_ptr[i] .. toggle_ptr[i+1]), strictly
+ * increasing, within [0, n_cycles * period_ps).  period_ps <= 2^24.
+ * Uploaded to the device.  Errors: GS_E_INVALID.  *stim_id receives the id. */
+gs_status gs_load_stimulus(gs_ctx *ctx, int32_t design, int32_t period_ps, int32_t n_cycles,
+                           const uint8_t *init, const int64_t *toggle_ptr, const int64_t *toggle_ps,
+                           int32_t *stim_id);
+
+/* Re-simulates cycles [cycle_begin, cycle_end) of stimulus `stim` on
+ * `design` and ADDS the per-net SAIF counts into the design's accumulators.
+ * The range is processed in windows that fit the memory budget; under the
+ * cycle-isolated model the result does not depend on the window size.
+ * Synchronous: returns after the device work is complete.  Errors:
+ * GS_E_STATE (no arcs), GS_E_INVALID (range), GS_E_NOMEM, GS_E_CAPACITY,
+ * GS_E_DEVICE. */
+gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end);
+
+/* Copies the design's accumulated SAIF counts, n_inputs + n_gates entries
+ * each, into caller arrays (any may be NULL); nonzero reset zeroes the
+ * accumulators afterwards. */
+gs_status gs_read_saif(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0, int64_t *t1, int32_t reset);
+
+/* Debug/spot-check read of one net's waveform in one cycle of the most
+ * recently simulated window of (design, stim): *init gets the value at
+ * t = 0, *n the number of edges, times[0 .. min(*n, cap)) the edge times in
+ * cycle-local ps.  GS_E_STATE if the cycle is not resident. */
+gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim, int32_t net, int32_t cycle,
+                           int32_t *init, int32_t *times, int32_t cap, int32_t *n);
+
+typedef struct {
+    int32_t n_inputs, n_gates, n_levels, max_pins;
+    int64_t n_fanin;
+    int32_t has_wires, zero_delay;
+    int32_t max_delay_ps, reserved;
+} gs_design_info;
+
+gs_status gs_get_design_info(gs_ctx *ctx, int32_t design, gs_design_info *info);
+
+/* Level of every gate (n_gates entries) as computed by the GPU levelizer. */
+gs_status gs_get_levels(gs_ctx *ctx, int32_t design, int32_t *level);
+
+typedef struct {
+    double   gate_eval_ms;      /* summed HIP-event time of gate-evaluation launches (timing on) */
+    double   expand_ms;         /* summed time of stimulus-expansion launches (timing on) */
+    double   wall_ms;           /* host wall time inside gs_simulate / gs_simulate_batch */
+    int64_t  gate_eval_launches;
+    int64_t  windows;
+    int64_t  window_retries;    /* windows redone after the transition arena filled up */
+    int64_t  gate_cycles;       /* gates x cycles simulated */
+    int64_t  spilled_lanes;     /* (net, cycle) lists longer than the on-chip staging cap */
+    int64_t  arena_words;       /* 32-bit transition slots used by the last window */
+    int64_t  reserved[6];
+} gs_stats;
+
+gs_status gs_get_stats(gs_ctx *ctx, gs_stats *st, int32_t reset);
+
+/* ---------------------------------------------------------------------
+ * Host-only checks (no device needed): the validation that the load calls
+ * run before touching the GPU, exposed for callers and tests.
+ * ------------------------------------------------------------------- */
+gs_status gs_check_netlist(int32_t n_cells, const uint8_t *n_pins, int32_t n_inputs, int32_t n_gates,
+                           const int32_t *cell_of_gate, const int64_t *fanin_ptr, const int32_t *fanin_net);
+gs_status gs_check_arcs(int32_t n_cells, const uint8_t *n_pins, int32_t n_gates, const int32_t *cell_of_gate,
+                        int64_t n_arcs, const gs_arc *arcs);
+gs_status gs_check_stimulus(int32_t n_inputs, int32_t period_ps, int32_t n_cycles, const uint8_t *init,
+                            const int64_t *toggle_ptr, const int64_t *toggle_ps);
+
+/* ---------------------------------------------------------------------
+ * Batching: many (design, stimulus, cycle range) jobs of uneven sizes in
+ * one schedule.  Level k of every job is evaluated by one launch over a
+ * work list of (job, gate, cycle tile) items; the launch sequence of a
+ * batch composition is captured into a HIP graph and replayed.  Per-job
+ * results are identical to running each job alone with gs_simulate; SAIF
+ * counts are added into each job's design accumulators.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t design;
+    int32_t stim;
+    int32_t cycle_begin;
+    int32_t cycle_end;
+} gs_job;
+
+gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job *jobs);
+
+/* ---------------------------------------------------------------------
+ * Serving: a resident request loop with continuous batching (the
+ * re-simulation step of GATSPI's glitch-optimization flow, Section 4).
+ * Requests are admitted while their device-memory footprint fits the free
+ * budget; admitted requests join the running level schedule at the next
+ * step, so their work overlaps on the device.
+ * ------------------------------------------------------------------- */
+#define GS_REQ_WINDOW 0     /* re-simulate cycles [cycle_begin, cycle_end) of (design, stim) */
+#define GS_REQ_EDIT   1     /* re-simulate the resident window with edited delay arcs */
+
+typedef struct {
+    int32_t gate;
+    int8_t  pin;
+    int8_t  cond_pin;       /* selects the record being edited; -1 = unconditional */
+    int8_t  cond_val;
+    int8_t  reserved;
+    int32_t rise_ps;        /* new delays */
+    int32_t fall_ps;
+} gs_arc_edit;
+
+typedef struct {
+    int32_t kind;           /* GS_REQ_WINDOW or GS_REQ_EDIT */
+    int32_t design;
+    int32_t stim;
+    int32_t cycle_begin;    /* GS_REQ_WINDOW */
+    int32_t cycle_end;
+    int32_t n_edits;        /* GS_REQ_EDIT */
+    const gs_arc_edit *edits;
+} gs_request;
+
+typedef struct {
+    int32_t  status;        /* GS_OK, or the request's error */
+    int32_t  n_nets;
+    const int64_t *tc;      /* library-owned until gs_release(ticket) */
+    const int64_t *t0;
+    const int64_t *t1;
+    int64_t  gate_cycles;   /* gates x cycles re-simulated for this request */
+    uint64_t t_submit_ns;   /* CLOCK_MONOTONIC */
+    uint64_t t_admit_ns;
+    uint64_t t_done_ns;
+} gs_result;
+
+/* Starts the serving loop: `resident_cycles` cycles starting at
+ * resident_begin of (design, stim) pairs given are simulated once and kept
+ * on the device as the base that delay-edit requests re-simulate against.
+ * max_queue bounds waiting requests (GS_E_BUSY beyond it). */
+gs_status gs_serve_start(gs_ctx *ctx, int32_t n_resident, const int32_t *designs, const int32_t *stims,
+                         const int32_t *resident_begin, const int32_t *resident_cycles, int32_t max_queue);
+gs_status gs_submit(gs_ctx *ctx, const gs_request *req, uint64_t *ticket);
+/* Non-blocking unless wait is nonzero.  Returns GS_E_BUSY while pending. */
+gs_status gs_poll(gs_ctx *ctx, uint64_t ticket, int32_t wait, gs_result *res);
+gs_status gs_release(gs_ctx *ctx, uint64_t ticket);
+gs_status gs_serve_stop(gs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GATESIM_H */

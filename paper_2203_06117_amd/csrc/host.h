@@ -1,0 +1,106 @@
+// Host-side structures of a context (not part of the public ABI).
+#pragma once
+
+#include "gatesim.h"
+#include "internal.h"
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+struct Design {
+    int32_t I = 0, G = 0, N = 0, L = 0;
+    int64_t F = 0;
+    int32_t max_pins = 0;
+    std::vector<uint8_t> gate_k;
+    std::vector<uint64_t> gate_truth;
+    std::vector<int64_t> fanin_ptr;
+    std::vector<int32_t> fanin_net;
+    std::vector<int32_t> level;          // per gate
+    std::vector<int32_t> perm;           // level order -> gate
+    std::vector<uint32_t> level_ptr;     // level l's gates: [level_ptr[l], level_ptr[l+1]), l = 1..L
+    std::vector<int32_t> level_kmax;     // largest pin count in each level
+    int32_t level_sweeps = 0;
+    // compiled delays per fanin slot
+    std::vector<int32_t> q, r0, f0, r1, f1, wr, wf;
+    bool arcs_loaded = false, has_wires = false;
+    int32_t zero_delay = 0, max_delay = 0, max_wire = 0;
+    uint64_t version = 0;
+    // device
+    int64_t *d_fanin_ptr = nullptr;
+    int32_t *d_fanin_net = nullptr;
+    int32_t *d_level = nullptr;
+    gs::GateRec *d_gates = nullptr;
+    gs::PinRec *d_pins = nullptr;
+    unsigned long long *d_saif = nullptr;    // tc[N], t1[N], t0[N]
+    unsigned long long *d_stage = nullptr;   // per-window staging, same layout
+};
+
+struct Stim {
+    int32_t design = -1, period = 0, n_cycles = 0;
+    int64_t n_toggles = 0;
+    uint8_t *d_init = nullptr;
+    int64_t *d_tp = nullptr;
+    int64_t *d_ts = nullptr;
+    std::vector<int64_t> tog_prefix;         // input toggles before cycle c
+};
+
+struct WindowBufs {
+    gs::ChunkHdr *hdr = nullptr;
+    uint16_t *ends = nullptr;
+    int32_t *times = nullptr;
+    uint64_t chunks = 0;                     // capacity in (net, tile) chunks
+    uint64_t words = 0;                      // capacity of `times`
+};
+
+struct LastWindow {
+    int32_t design = -1, stim = -1, c0 = 0, cycles = 0;
+    uint64_t chunk_base = 0;
+    int32_t n_nets = 0;
+};
+
+struct ServeState;
+
+struct gs_ctx {
+    gs_options opt;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    uint64_t budget = 0;
+    std::vector<uint8_t> cell_k;
+    std::vector<uint64_t> cell_truth;
+    std::vector<Design *> designs;
+    std::vector<Stim *> stims;
+    WindowBufs win;
+    LastWindow last;
+    gs::Seg *d_segs = nullptr;
+    size_t segs_cap = 0;
+    unsigned long long *d_misc = nullptr;    // [0] bump, [1] flags x2 (u32), [2] flags, [4..] scratch counters
+    std::vector<hipEvent_t> events;
+    gs_stats stats{};
+    hipGraphExec_t graph_exec = nullptr;
+    // batching: cached graph key
+    std::vector<int64_t> graph_key;
+    // serving
+    ServeState *serve = nullptr;
+    bool serving = false;
+};
+
+gs_status gs_fail(gs_ctx *ctx, gs_status code, const char *fmt, ...);
+uint64_t gs_now_ns();
+void gs_dev_free(void *p);
+void gs_window_release(gs_ctx *ctx, WindowBufs *w);
+gs_status gs_window_reserve(gs_ctx *ctx, WindowBufs *w, uint64_t n_chunks, uint64_t words);
+uint64_t gs_header_bytes(uint64_t n_nets, int32_t cycles);
+uint64_t gs_arena_guess(uint64_t n_nets, int32_t cycles, int64_t toggles);
+gs_status gs_check_ranges(gs_ctx *ctx, const Design *d, const Stim *s, int32_t b, int32_t e);
+gs::WinView gs_make_view(gs_ctx *ctx, const WindowBufs &w, int32_t cycles, int32_t period, uint64_t chunk_base,
+                         uint64_t n_chunks_used);
+gs_status gs_ensure_segs(gs_ctx *ctx, size_t n);
+hipEvent_t gs_event(gs_ctx *ctx, size_t i);
+void gs_serve_shutdown(gs_ctx *ctx);

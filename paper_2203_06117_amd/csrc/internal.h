@@ -1,0 +1,105 @@
+// Internal structures shared by the host core (host.cpp) and the gfx950
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+constexpr int kLanes = 64;                  // wavefront size on CDNA; one lane per cycle of a tile
+constexpr int32_t kInf = 0x7fffffff;        // end-of-waveform time (Algorithm 1's EOW)
+constexpr uint32_t kMaxChunk = 65535;       // transitions per (net, 64-cycle tile): 16-bit lane ends
+
+// One gate in level order (the level partition of Section 3), 32 bytes.
+struct GateRec {
+    uint32_t out;       // output net id
+    uint32_t pin0;      // index of its first PinRec
+    uint32_t k;         // number of pins
+    uint32_t pad;
+    uint64_t truth;     // truth bits, pin 0 = least significant bit of the index
+    uint64_t pad2;
+};
+
+// One gate pin (fanin arc), 32 bytes.  The delay of this pin's arc for an
+// output edge is r/f "0" while pin q of the gate is 0 and r/f "1" while it
+// is 1 (an unconditional arc has r0 == r1 and f0 == f1).
+struct PinRec {
+    int32_t net;
+    int32_t q;
+    int32_t r0, f0, r1, f1;
+    int32_t wr, wf;     // interconnect rise / fall delay
+};
+
+// Where the transitions of one (net, 64-cycle tile) live: `off` is the word
+// offset of the chunk in the window's transition arena; bit l of `mask` is
+// the value of the net at t = 0 of the tile's cycle l.
+struct ChunkHdr {
+    uint64_t off;
+    uint64_t mask;
+};
+
+// A window of cycles resident on the device.
+//   hdr[net * n_tiles + tile]
+//   ends[(net * n_tiles + tile) * 64 + lane]: inclusive prefix sum of the
+//     per-cycle transition counts inside the chunk
+//   times[hdr.off + ...]: cycle-local transition times, lane after lane
+struct WinView {
+    ChunkHdr *hdr;
+    uint16_t *ends;
+    int32_t *times;
+    unsigned long long *bump;      // words of `times` handed out
+    unsigned int *flags;           // [0] arena full, [1] chunk over 65535, [2] spilled lanes
+    uint64_t cap_words;
+    int32_t n_tiles;
+    int32_t n_cycles;              // cycles in this window
+    int32_t period;
+    int32_t pad;
+};
+
+struct SaifAcc {
+    unsigned long long *tc;
+    unsigned long long *t0;
+    unsigned long long *t1;
+};
+
+// One piece of a gate-evaluation launch: the gates [gate_begin,
+// gate_begin + n_gates) of one level of one instance, all tiles of its
+// window.  Wave w of the launch belongs to the segment whose
+// [wave_begin, wave_begin + n_gates * n_tiles) holds it.
+struct Seg {
+    uint64_t wave_begin;
+    const GateRec *gates;
+    const PinRec *pins;
+    uint32_t gate_begin;
+    uint32_t n_gates;
+    WinView win;
+    SaifAcc saif;
+};
+
+// Device copy of one stimulus.
+struct StimView {
+    const uint8_t *init;
+    const int64_t *toggle_ptr;
+    const int64_t *toggle_ps;
+    int32_t n_inputs;
+    int32_t period;
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int *p, uint64_t n, unsigned int v, hipStream_t s);
+hipError_t launch_add_u64(unsigned long long *dst, const unsigned long long *src, uint64_t n, hipStream_t s);
+
+hipError_t launch_level_init(int32_t *level, int32_t n_inputs, int32_t n_gates, hipStream_t s);
+hipError_t launch_level_step(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t *level,
+                             int32_t n_inputs, int32_t n_gates, unsigned int *counters, hipStream_t s);
+hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n_gates,
+                               unsigned int *cursor, int32_t *perm, int count_only, hipStream_t s);
+
+hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, hipStream_t s);
+
+hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires,
+                            int32_t cap, int32_t wpb, int32_t kmax, hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact.
+
+All results are integers (picosecond times, counts, SAIF sums), so the bar
+is equality.  Cases cover hand-derived circuits, seeded random netlists with
+wires, conditional arcs, multi-edge inputs and zero-delay mode, window and
+tile invariance (ragged last tiles, window boundaries, forced arena
+retries, forced on-chip staging overflow), the levelizer, error paths, and
+the 1M-gate workload in the launch configuration the benchmark times.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_06117_amd import synth
+from tests.handmade import work
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_06117_amd import gatesim
+    return gatesim
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_saif(G, w, b=0, e=None, probes=(), **opt):
+    C = w["stimulus"]["n_cycles"]
+    e = C if e is None else e
+    with G.GateSim(**opt) as sim:
+        d, s = sim.load_work(w)
+        sim.simulate(d, s, b, e)
+        tc, t0, t1 = sim.read_saif(d)
+        waves = [sim.read_waveform(d, s, n, c) for n, c in probes]
+        st = sim.stats()
+    return tc, t0, t1, waves, st
+
+
+def assert_same(w, got, ref, tag=""):
+    tc, t0, t1 = got[:3]
+    for name, a, b in (("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"])):
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"{tag}: {name} differs on {len(bad)} nets, first {bad[:8]} "
+                                 f"gpu {a[bad[:8]]} oracle {b[bad[:8]]}")
+
+
+def test_handmade_golden(G):
+    for f in sorted(os.listdir(GOLDEN)):
+        if not f.endswith(".json"):
+            continue
+        fx = json.load(open(os.path.join(GOLDEN, f)))
+        wires = [tuple(x) for x in fx["wires"]] if fx.get("wires") else None
+        w = work(fx["n_inputs"], [tuple(g) for g in fx["gates"]], [tuple(a) for a in fx["arcs"]],
+                 fx["toggles"], fx["init"], period=fx["period"], n_cycles=fx["n_cycles"], wires=wires)
+        say("golden", f)
+        probes = [(x["net"], x["cycle"]) for x in fx["expect"]]
+        got = gpu_saif(G, w, probes=probes)
+        for x, (init, times, n) in zip(fx["expect"], got[3]):
+            assert (init, times) == (x["init"], x["times"]), (f, x)
+        assert_same(w, got, oracle.simulate(w), f)
+
+
+@pytest.mark.parametrize("cell", ["BUF", "INV"])
+def test_pulse_grid(G, cell):
+    """The inertial closed-form grid (every leading/trailing delay and width)."""
+    cases = [(dl, dt, wd) for dl in range(1, 13) for dt in range(1, 13) for wd in range(1, 15)]
+    n = len(cases)
+    gates, arcs, tog = [], [], []
+    for g, (dl, dt, wd) in enumerate(cases):
+        gates.append((cell, [g]))
+        rise, fall = (dl, dt) if cell == "BUF" else (dt, dl)
+        arcs.append((g, 0, -1, 0, rise, fall))
+        tog.append([10 + 100 * c + (wd if c % 2 else 0) for c in range(2)] + [210, 210 + wd])
+    w = work(n, gates, arcs, tog, [0] * n, period=100, n_cycles=3)
+    say("pulse grid", cell, n)
+    got = gpu_saif(G, w)
+    assert_same(w, got, oracle.simulate(w), cell)
+
+
+@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "multi-edge"])
+def test_random_small(G, mode):
+    for seed in range(20):
+        rng = np.random.default_rng(seed + 100)
+        gates = int(rng.integers(50, 900))
+        levels = int(rng.integers(2, 30))
+        C = int(rng.integers(1, 200))
+        T = int(rng.integers(60, 600))
+        zero = mode == "zero"
+        w = synth.small_random(seed + 7000, gates, int(rng.integers(3, 40)), min(levels, gates), C, T,
+                               float(rng.uniform(0.05, 0.6)), 0 if zero else 1, 0 if zero else int(rng.integers(2, 80)),
+                               cond_frac=0.3 if "cond" in mode else 0.0,
+                               wire=(1, int(rng.integers(1, 25))) if "wires" in mode else None,
+                               extra=3 if mode in ("multi-edge", "wires") else 0, extra_p=0.3,
+                               skew=min(50, T - 1))
+        say("random", mode, seed, gates, levels, C, T)
+        got = gpu_saif(G, w, window_cycles=int(rng.choice([0, 64, 100, 37])))
+        assert_same(w, got, oracle.simulate(w), f"{mode} seed {seed}")
+
+
+def test_tiny_config_waveforms(G):
+    """2,000 gates x 100 cycles: all SAIF counts plus a sample of full
+    waveforms (the analog of the paper's spot-checks)."""
+    w = synth.tiny()
+    rng = np.random.default_rng(0)
+    N = 64 + 2000
+    probes = [(int(n), int(c)) for n, c in zip(rng.integers(0, N, 400), rng.integers(0, 100, 400))]
+    ref = oracle.simulate(w, probes=probes)
+    got = gpu_saif(G, w, probes=probes)
+    assert_same(w, got, ref, "tiny")
+    for (n, c), (gi, gt, gn), (oi, ot, on) in zip(probes, got[3], ref["probes"]):
+        assert (gi, gt, gn) == (oi, ot, on), (n, c)
+
+
+@pytest.mark.parametrize("opt", [dict(window_cycles=64), dict(window_cycles=37), dict(window_cycles=100),
+                                 dict(lds_cap=4), dict(lds_cap=32, waves_per_block=1),
+                                 dict(waves_per_block=8, lds_cap=8), dict(window_cycles=300, hbm_budget=1_900_000)])
+def test_invariance(G, opt):
+    """Same SAIF for every window size, staging cap, block shape and for a
+    budget so small that windows shrink and the transition arena refills."""
+    w = synth.small_random(42, 1500, 40, 40, 300, 500, 0.4, 2, 70, cond_frac=0.2, extra=2, extra_p=0.3)
+    say("invariance", opt)
+    got = gpu_saif(G, w, **opt)
+    assert_same(w, got, oracle.simulate(w), str(opt))
+    if opt.get("lds_cap") == 4:
+        assert got[4]["spilled_lanes"] > 0
+    if opt.get("hbm_budget"):
+        assert got[4]["window_retries"] > 0
+
+
+def test_cycle_subranges(G):
+    """Accumulating disjoint sub-ranges equals the whole range; a range can
+    start and end anywhere (ragged tiles on both sides)."""
+    w = synth.small_random(9, 800, 30, 20, 260, 700, 0.3, 3, 60, cond_frac=0.2)
+    ref = oracle.simulate(w)
+    with G.GateSim(window_cycles=90) as sim:
+        d, s = sim.load_work(w)
+        for b, e in ((0, 1), (1, 63), (63, 64), (64, 200), (200, 200), (200, 260)):
+            sim.simulate(d, s, b, e)
+        got = sim.read_saif(d)
+    assert_same(w, got, ref, "subranges")
+
+
+def test_levelizer_matches_oracle(G):
+    w = synth.small_random(13, 3000, 50, 60, 2, 100, 0.3, 1, 5)
+    o = oracle.Oracle(w["netlist"], w["arcs"])
+    with G.GateSim() as sim:
+        d, s = sim.load_work(w)
+        lv = sim.levels(d)
+        info = sim.design_info(d)
+    exp = np.array([o.level(50 + g) for g in range(3000)])
+    assert np.array_equal(lv, exp)
+    assert info.n_levels == exp.max()
+
+
+def test_errors(G):
+    with G.GateSim() as sim:
+        sim.load_cells(synth.CELL_PINS, synth.CELL_TRUTH)
+        # a two-gate loop: NAND2(in, g1) -> g0 ; BUF(g0) -> g1
+        with pytest.raises(G.GateSimError) as e:
+            sim.load_netlist(1, [synth.NAND2, synth.BUF], [0, 2, 3], [0, 2, 1])
+        assert e.value.status == G.GS_E_NOT_DAG
+        w = synth.small_random(3, 100, 8, 5, 10, 200, 0.3, 2, 9)
+        d, s = sim.load_work(w, cells_loaded=True)
+        with pytest.raises(G.GateSimError) as e:
+            sim.simulate(d, s, 5, 11)
+        assert e.value.status == G.GS_E_INVALID
+        with pytest.raises(G.GateSimError) as e:
+            sim.read_waveform(d, s, 3, 0)
+        assert e.value.status == G.GS_E_STATE
+        n = w["netlist"]
+        d2 = sim.load_netlist(n["n_inputs"], n["cell_of_gate"], n["fanin_ptr"], n["fanin_net"])
+        s2 = sim.load_stimulus(d2, 200, 10, w["stimulus"]["init"], w["stimulus"]["toggle_ptr"],
+                               w["stimulus"]["toggle_ps"])
+        with pytest.raises(G.GateSimError) as e:
+            sim.simulate(d2, s2, 0, 10)                       # no arcs yet
+        assert e.value.status == G.GS_E_STATE
+        sim.simulate(d, s, 0, 0)                              # empty range is fine
+
+
+def test_edge_cases(G):
+    # inputs that never toggle, a gate-free design, single-cycle stimulus
+    w = synth.small_random(21, 400, 12, 10, 1, 300, 0.0, 2, 40)
+    assert_same(w, gpu_saif(G, w), oracle.simulate(w), "no toggles")
+    w = work(3, [], [], [[5, 50], [], [7]], [0, 1, 1], period=100, n_cycles=1)
+    assert_same(w, gpu_saif(G, w), oracle.simulate(w), "no gates")
+    # a toggle at local time 0 and at the last picosecond of a cycle
+    w = work(2, [("XOR2", [0, 1]), ("NAND2", [0, 2])], (7, 5), [[0, 99, 100], [199]], [0, 1], period=100, n_cycles=2)
+    assert_same(w, gpu_saif(G, w), oracle.simulate(w), "boundary toggles")
+
+
+def test_scale_config_sample(G):
+    """The 1M-gate workload in the benchmark's launch configuration
+    (1,000-cycle windows from cycle 0, default tile and staging).  The GPU
+    runs cycles [0, 990) and [0, 1010); under cycle isolation their SAIF
+    difference is cycles 990..1009, which straddle the first window boundary
+    and are compared net by net with the oracle, plus a waveform sample from
+    the resident second window."""
+    w = synth.scale(n_cycles=1100)
+    b, e = 990, 1010
+    N = 20_000 + 1_000_000
+    rng = np.random.default_rng(1)
+    probes = [(int(n), int(c)) for n, c in zip(rng.integers(0, N, 200), rng.integers(1000, 1010, 200))]
+    say("scale: oracle")
+    ref = oracle.simulate(w, b, e, probes=probes)
+    say("scale: gpu")
+    with G.GateSim(window_cycles=1000) as sim:
+        d, s = sim.load_work(w)
+        sim.simulate(d, s, 0, b)
+        lo = sim.read_saif(d, reset=True)
+        sim.simulate(d, s, 0, e)
+        hi = sim.read_saif(d, reset=True)
+        waves = [sim.read_waveform(d, s, n, c) for n, c in probes]
+    got = tuple(h - l for h, l in zip(hi, lo))
+    assert_same(w, got, ref, "scale")
+    for (n, c), g_, o_ in zip(probes, waves, ref["probes"]):
+        assert g_ == o_, (n, c)

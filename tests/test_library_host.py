@@ -1,0 +1,99 @@
+"""CPU-side checks of the HIP library: it loads, exports every symbol the
+header declares, and its host-only validation accepts good inputs and
+rejects malformed ones with the documented status codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2203_06117_amd import synth
+from paper_2203_06117_amd import gatesim as G
+from tests.handmade import work
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gatesim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(G._lib, n), n
+    assert names == G.EXPORTS
+
+
+def test_arc_struct_layout():
+    assert G.ARC_DTYPE.itemsize == 16
+    assert G.ARC_DTYPE.fields["rise"][1] == 8
+
+
+def test_check_netlist():
+    w = synth.tiny()
+    n = w["netlist"]
+    assert G.check_netlist(n["cell_pins"], 64, n["cell_of_gate"], n["fanin_ptr"], n["fanin_net"]) == G.GS_OK
+    bad = n["fanin_net"].copy()
+    bad[5] = 64 + 2000
+    assert G.check_netlist(n["cell_pins"], 64, n["cell_of_gate"], n["fanin_ptr"], bad) == G.GS_E_INVALID
+    assert "out of range" in G.last_error()
+    cog = n["cell_of_gate"].copy()
+    cog[3] = 99
+    assert G.check_netlist(n["cell_pins"], 64, cog, n["fanin_ptr"], n["fanin_net"]) == G.GS_E_INVALID
+    # arity mismatch: an INV given two fanins
+    w2 = work(2, [("INV", [0, 1])], (1, 1), [[], []], [0, 0])
+    n2 = w2["netlist"]
+    assert G.check_netlist(n2["cell_pins"], 2, n2["cell_of_gate"], n2["fanin_ptr"], n2["fanin_net"]) == G.GS_E_INVALID
+
+
+def test_check_arcs():
+    w = synth.small_random(3, 200, 10, 8, 5, 500, 0.3, 2, 30, cond_frac=0.3)
+    n, a = w["netlist"], w["arcs"]
+    assert G.check_arcs(n["cell_pins"], n["cell_of_gate"], a) == G.GS_OK
+    # drop one record: some pin state loses its delay
+    cut = {k: v[1:] for k, v in a.items()}
+    assert G.check_arcs(n["cell_pins"], n["cell_of_gate"], cut) == G.GS_E_INVALID
+    # duplicate a record: two records for one pin state
+    dup = {k: np.concatenate([v, v[:1]]) for k, v in a.items()}
+    assert G.check_arcs(n["cell_pins"], n["cell_of_gate"], dup) == G.GS_E_INVALID
+    # mixing zero and positive delays
+    z = {k: v.copy() for k, v in a.items()}
+    z["rise"][0] = 0
+    assert G.check_arcs(n["cell_pins"], n["cell_of_gate"], z) == G.GS_E_INVALID
+    # a conditional pair alone covers the pin; with a fallback record too it stays valid
+    h = work(2, [("XOR2", [0, 1])], [(0, 0, 1, 0, 3, 4), (0, 0, 1, 1, 5, 6), (0, 1, -1, 0, 2, 2)], [[], []], [0, 0])
+    assert G.check_arcs(h["netlist"]["cell_pins"], h["netlist"]["cell_of_gate"], h["arcs"]) == G.GS_OK
+    h = work(2, [("XOR2", [0, 1])], [(0, 0, 1, 0, 3, 4), (0, 0, -1, 0, 5, 6), (0, 1, -1, 0, 2, 2)], [[], []], [0, 0])
+    assert G.check_arcs(h["netlist"]["cell_pins"], h["netlist"]["cell_of_gate"], h["arcs"]) == G.GS_OK
+    # a condition on the arc's own pin is rejected
+    h = work(2, [("XOR2", [0, 1])], [(0, 0, 0, 0, 3, 4), (0, 0, -1, 0, 5, 6), (0, 1, -1, 0, 2, 2)], [[], []], [0, 0])
+    assert G.check_arcs(h["netlist"]["cell_pins"], h["netlist"]["cell_of_gate"], h["arcs"]) == G.GS_E_INVALID
+
+
+def test_check_stimulus():
+    s = synth.make_stimulus(4, 10, 50, 100, 0.4, skew=20, extra=2, extra_p=0.3)
+    args = (10, 100, 50, s["init"], s["toggle_ptr"], s["toggle_ps"])
+    assert G.check_stimulus(*args) == G.GS_OK
+    ts = s["toggle_ps"].copy()
+    i = int(np.argmax(np.diff(s["toggle_ptr"])))
+    k = int(s["toggle_ptr"][i])
+    ts[k + 1] = ts[k]
+    assert G.check_stimulus(10, 100, 50, s["init"], s["toggle_ptr"], ts) == G.GS_E_INVALID
+    ts = s["toggle_ps"].copy()
+    ts[-1] = 50 * 100
+    assert G.check_stimulus(10, 100, 50, s["init"], s["toggle_ptr"], ts) == G.GS_E_INVALID
+    assert G.check_stimulus(10, 0, 50, s["init"], s["toggle_ptr"], s["toggle_ps"]) == G.GS_E_INVALID
+    assert G.check_stimulus(10, (1 << 24) + 1, 50, s["init"], s["toggle_ptr"], s["toggle_ps"]) == G.GS_E_INVALID
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(G.GateSimError) as e:
+        G.GateSim()
+    assert e.value.status == G.GS_E_DEVICE
