@@ -835,8 +835,8 @@ extern "C" gs_status gs_read_saif(gs_ctx *ctx, int32_t design, int64_t *tc, int6
     const size_t n = (size_t)d->N;
     if (n) {
         if (tc) HIPCHK(hipMemcpyAsync(tc, d->d_saif, n * 8, hipMemcpyDeviceToHost, hs));
-        if (t0) HIPCHK(hipMemcpyAsync(t0, d->d_saif + 2 * n, n * 8, hipMemcpyDeviceToHost, hs));
-        if (t1) HIPCHK(hipMemcpyAsync(t1, d->d_saif + n, n * 8, hipMemcpyDeviceToHost, hs));
+        if (t0) HIPCHK(hipMemcpyAsync(t0, d->d_saif + n, n * 8, hipMemcpyDeviceToHost, hs));
+        if (t1) HIPCHK(hipMemcpyAsync(t1, d->d_saif + 2 * n, n * 8, hipMemcpyDeviceToHost, hs));
         if (reset) HIPCHK(launch_fill_u64(d->d_saif, 3 * n, 0ull, hs));
     }
     HIPCHK(hipStreamSynchronize(hs));
