@@ -272,7 +272,12 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
         gs_destroy(ctx);
         return gs_fail(nullptr, GS_E_NOMEM, "small allocation failed");
     }
-    ctx->d_misc = (unsigned long long *)p;   // [0] bump, [1..] flags
+    ctx->d_misc = (unsigned long long *)p;   // [1..2] flags, [4..] counters
+    if (dev_alloc(ctx, &p, sizeof(unsigned long long) * kMaxStripes * kBumpStride) != GS_OK) {
+        gs_destroy(ctx);
+        return gs_fail(nullptr, GS_E_NOMEM, "small allocation failed");
+    }
+    ctx->d_bump = (unsigned long long *)p;
     *out = ctx;
     return GS_OK;
 }
@@ -297,6 +302,7 @@ extern "C" gs_status gs_destroy(gs_ctx *ctx)
     gs_window_release(ctx, &ctx->win);
     gs_dev_free(ctx->d_segs);
     gs_dev_free(ctx->d_misc);
+    gs_dev_free(ctx->d_bump);
     for (auto &ev : ctx->events) (void)hipEventDestroy(ev);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -666,9 +672,13 @@ WinView gs_make_view(gs_ctx *ctx, const WindowBufs &w, int32_t cycles, int32_t p
     v.hdr = w.hdr + chunk_base;
     v.ends = w.ends + chunk_base * kLanes;
     v.times = w.times;
-    v.bump = ctx->d_misc;
+    // stripes: a power of two, each slice at least 4096 words
+    uint32_t stripes = 1;
+    while (stripes < (uint32_t)kMaxStripes && w.words / (2ull * stripes) >= 4096) stripes *= 2;
+    v.bump = ctx->d_bump;
     v.flags = (unsigned int *)(ctx->d_misc + 1);
-    v.cap_words = w.words;
+    v.slice_words = w.words / stripes;
+    v.stripe_mask = stripes - 1;
     v.n_tiles = (cycles + kLanes - 1) / kLanes;
     v.n_cycles = cycles;
     v.period = period;
@@ -715,6 +725,9 @@ static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t
     SaifAcc stage{d->d_stage, d->d_stage + d->N, d->d_stage + 2 * (size_t)d->N};
     // segment table: one per level
     std::vector<Seg> segs(std::max(1, d->L));
+    // stripe salt: each launch continues the round robin where the last one ended
+    const uint32_t wpb = (uint32_t)ctx->opt.waves_per_block;
+    uint64_t salt = ((uint64_t)d->I * tiles + 3) / 4;
     for (int32_t l = 1; l <= d->L; l++) {
         Seg &g = segs[l - 1];
         std::memset(&g, 0, sizeof(g));
@@ -725,16 +738,19 @@ static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t
         g.n_gates = d->level_ptr[l + 1] - d->level_ptr[l];
         g.win = v;
         g.saif = stage;
+        g.salt = (uint32_t)salt;
+        salt += ((uint64_t)g.n_gates * tiles + wpb - 1) / wpb;
     }
     if ((st = gs_ensure_segs(ctx, segs.size()))) return st;
     HIPCHK(hipMemcpyAsync(ctx->d_segs, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice, hs));
-    HIPCHK(launch_fill_u64(ctx->d_misc, 4, 0ull, hs));                   // bump + flags
+    HIPCHK(launch_fill_u64(ctx->d_misc, 4, 0ull, hs));                   // flags
+    HIPCHK(launch_fill_u64(ctx->d_bump, (uint64_t)kMaxStripes * kBumpStride, 0ull, hs));
     HIPCHK(launch_fill_u64(d->d_stage, 3 * (uint64_t)d->N, 0ull, hs));
     const bool timing = ctx->opt.timing != 0;
     size_t ev = 0;
     if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     StimView sv{s->d_init, s->d_tp, s->d_ts, d->I, s->period};
-    HIPCHK(launch_expand(sv, v, stage, c0, hs));
+    HIPCHK(launch_expand(sv, v, stage, c0, 0u, hs));
     if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     for (int32_t l = 1; l <= d->L; l++) {
         const uint64_t nw = (uint64_t)segs[l - 1].n_gates * tiles;
@@ -744,8 +760,12 @@ static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t
         if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     }
     unsigned long long hflags[4];
+    std::vector<unsigned long long> hb((size_t)kMaxStripes * kBumpStride);
     HIPCHK(hipMemcpyAsync(hflags, ctx->d_misc, sizeof(hflags), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipMemcpyAsync(hb.data(), ctx->d_bump, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost, hs));
     HIPCHK(hipStreamSynchronize(hs));
+    uint64_t used = 0;
+    for (uint32_t i = 0; i <= v.stripe_mask; i++) used += std::min<uint64_t>(hb[(size_t)i * kBumpStride], v.slice_words);
     const unsigned int *f32 = (const unsigned int *)(hflags + 1);
     if (timing) {
         float ms = 0;
@@ -758,7 +778,7 @@ static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t
     }
     ctx->stats.gate_eval_launches += d->L;
     ctx->stats.spilled_lanes += f32[2];
-    ctx->stats.arena_words = (int64_t)hflags[0];
+    ctx->stats.arena_words = (int64_t)used;
     if (f32[1]) return gs_fail(ctx, GS_E_CAPACITY, "more than %u transitions in one (net, 64-cycle tile)", kMaxChunk);
     if (f32[0]) {
         *retry = true;

@@ -80,7 +80,8 @@ struct gs_ctx {
     LastWindow last;
     gs::Seg *d_segs = nullptr;
     size_t segs_cap = 0;
-    unsigned long long *d_misc = nullptr;    // [0] bump, [1] flags x2 (u32), [2] flags, [4..] scratch counters
+    unsigned long long *d_misc = nullptr;    // [0] unused, [1] flags x2 (u32), [2] flags, [4..] scratch counters
+    unsigned long long *d_bump = nullptr;    // kMaxStripes stripe counters, kBumpStride apart
     std::vector<hipEvent_t> events;
     gs_stats stats{};
     hipGraphExec_t graph_exec = nullptr;

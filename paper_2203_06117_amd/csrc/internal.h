@@ -48,14 +48,20 @@ struct WinView {
     ChunkHdr *hdr;
     uint16_t *ends;
     int32_t *times;
-    unsigned long long *bump;      // words of `times` handed out
+    unsigned long long *bump;      // one counter per stripe, kBumpStride apart: words handed out in the stripe
     unsigned int *flags;           // [0] arena full, [1] chunk over 65535, [2] spilled lanes
-    uint64_t cap_words;
+    uint64_t slice_words;          // arena words owned by each stripe
     int32_t n_tiles;
     int32_t n_cycles;              // cycles in this window
     int32_t period;
-    int32_t pad;
+    uint32_t stripe_mask;          // stripes - 1 (a power of two)
 };
+
+// The transition arena is split into stripes, each with its own bump
+// counter on its own 256-byte line, so that the per-wave reservations of a
+// launch spread over many addresses instead of serialising on one.
+constexpr int kMaxStripes = 512;
+constexpr int kBumpStride = 32;             // u64 counters between stripes (256 B)
 
 struct SaifAcc {
     unsigned long long *tc;
@@ -73,6 +79,8 @@ struct Seg {
     const PinRec *pins;
     uint32_t gate_begin;
     uint32_t n_gates;
+    uint32_t salt;                 // added to the block index to pick an arena stripe
+    uint32_t pad;
     WinView win;
     SaifAcc saif;
 };
@@ -97,7 +105,7 @@ hipError_t launch_level_step(const int64_t *fanin_ptr, const int32_t *fanin_net,
 hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n_gates,
                                unsigned int *cursor, int32_t *perm, int count_only, hipStream_t s);
 
-hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, hipStream_t s);
+hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, uint32_t salt, hipStream_t s);
 
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires,
                             int32_t cap, int32_t wpb, int32_t kmax, hipStream_t s);

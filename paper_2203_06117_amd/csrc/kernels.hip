@@ -45,7 +45,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // (and writes an empty, in-bounds chunk) when the arena is full or the chunk
 // exceeds 16-bit lane ends; the host then redoes the window.
 __device__ __forceinline__ bool place_chunk(const WinView &win, uint64_t ci, uint32_t incl, uint32_t total,
-                                            uint64_t mask, int lane, uint64_t &base)
+                                            uint64_t mask, int lane, uint32_t salt, uint64_t &base)
 {
     bool ok = true;
     if (total > kMaxChunk) {
@@ -54,12 +54,14 @@ __device__ __forceinline__ bool place_chunk(const WinView &win, uint64_t ci, uin
     }
     uint64_t b = 0;
     if (ok && total > 0) {
-        if (lane == 0) b = atomicAdd(win.bump, (unsigned long long)total);
+        const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
+        if (lane == 0) b = atomicAdd(win.bump + (size_t)stripe * kBumpStride, (unsigned long long)total);
         b = uniform64(b);
-        if (b + total > win.cap_words) {
+        if (b + total > win.slice_words) {
             if (lane == 0) atomicOr(&win.flags[0], 1u);
             ok = false;
         }
+        b += (uint64_t)stripe * win.slice_words;
     }
     win.ends[ci * kLanes + lane] = ok ? (uint16_t)incl : (uint16_t)0;
     if (lane == 0) {
@@ -210,7 +212,7 @@ __device__ __forceinline__ int64_t lower_bound64(const int64_t *__restrict__ a, 
 }
 
 __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, SaifAcc acc, int32_t cycle0,
-                                                     uint64_t n_waves)
+                                                     uint32_t salt, uint64_t n_waves)
 {
     const int lane = threadIdx.x & (kLanes - 1);
     const uint32_t wib = uniform(threadIdx.x / kLanes);
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     const uint64_t mask = __ballot(v0 != 0);
     const uint64_t ci = (uint64_t)i * ntile + tile;
     uint64_t base;
-    const bool ok = place_chunk(win, ci, incl, total, mask, lane, base);
+    const bool ok = place_chunk(win, ci, incl, total, mask, lane, salt, base);
     // time at 1 inside [0, T): final value * T - sum of rising-edge times + sum of falling-edge times
     int v = v0, a = 0;
     for (uint32_t j = 0; j < cnt; j++) {
@@ -255,13 +257,14 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     }
 }
 
-hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, hipStream_t s)
+hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, uint32_t salt, hipStream_t s)
 {
     uint64_t n_waves = (uint64_t)st.n_inputs * (uint64_t)win.n_tiles;
     if (n_waves == 0) return hipSuccess;
     const int wpb = 4;
     uint64_t blocks = (n_waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, st, win, acc, cycle0, n_waves);
+    hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, st, win, acc, cycle0, salt,
+                       n_waves);
     return hipGetLastError();
 }
 
@@ -424,7 +427,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
     const uint64_t mask = __ballot(active && y0);
     const uint64_t ci = (uint64_t)g.out * (uint32_t)win.n_tiles + tile;
     uint64_t base;
-    const bool ok = place_chunk(win, ci, incl, total, mask, lane, base);
+    const bool ok = place_chunk(win, ci, incl, total, mask, lane, sg.salt, base);
     const uint32_t excl = incl - ucnt;
     if (ok) {
         int32_t *out = win.times + base + excl;
