@@ -51,10 +51,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cycles", type=int, default=10_000)
     ap.add_argument("--window", type=int, default=1000)
-    ap.add_argument("--lds-cap", type=int, default=16)
+    ap.add_argument("--lds-cap", type=int, default=8)
+    ap.add_argument("--tpw", type=int, default=4)
     ap.add_argument("--wpb", type=int, default=4)
     ap.add_argument("--cpu-cycles", type=int, default=30, help="oracle sample: first N cycles (0 = skip)")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU cycle sharding is a design "
@@ -78,13 +81,21 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     sim = GateSim(device=0, stream=stream, window_cycles=args.window, lds_cap=args.lds_cap,
-                  waves_per_block=args.wpb, timing=not args.no_timing)
+                  waves_per_block=args.wpb, timing=not args.no_timing, tiles_per_wave=args.tpw)
     t_load = time.time()
     d, s = sim.load_work(w)
     load_s = time.time() - t_load
     info = sim.design_info(d)
     print(f"[bench] loaded in {load_s:.1f}s, {info.n_levels} levels", file=sys.stderr, flush=True)
 
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib << 18
+        a = torch.ones(n, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        torch.add(a, 1, out=b)          # one elementwise kernel: reads n*4 bytes, writes n*4 bytes
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr, flush=True)
+        del a, b
     for i in range(args.warmup):
         sim.simulate(d, s, 0, C)
         sim.read_saif(d, reset=True)
@@ -153,7 +164,7 @@ def main():
         "config": {"workload": "scale-1M", "gates": Gn, "inputs": net["n_inputs"], "levels": info.n_levels,
                    "cycles": C, "period_ps": stim["period"], "toggle_p": 0.15, "delays_ps": "5-80",
                    "cond_frac": 0.10, "window_cycles": args.window, "lds_cap": args.lds_cap,
-                   "waves_per_block": args.wpb},
+                   "waves_per_block": args.wpb, "tiles_per_wave": args.tpw},
         "kernel_gate_cycles_per_s": round(gate_cycles / (st["gate_eval_ms"] / 1e3), 1) if roofline else None,
         "transitions_per_gate_cycle": round(a_bar, 4),
         "spilled_lanes": st["spilled_lanes"],

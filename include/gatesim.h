@@ -78,11 +78,12 @@ typedef struct {
     void    *arena;           /* optional caller-owned device buffer used for all waveform storage */
     uint64_t arena_bytes;
     int32_t  window_cycles;   /* cycles per window; 0 = as many as fit the budget, capped at 4096 */
-    int32_t  lds_cap;         /* transitions per (net, cycle) staged on chip before the spill path: 4, 8, 16 or 32; 0 = 16 */
+    int32_t  lds_cap;         /* transitions per (net, cycle) staged on chip before the spill path: 4, 8, 16 or 32; 0 = 8 */
     int32_t  waves_per_block; /* 1, 2, 4 or 8; 0 = 4 */
     int32_t  schedule;        /* GS_SCHED_LEVELS or GS_SCHED_GRAPH */
     int32_t  timing;          /* nonzero: time every gate-evaluation launch with HIP events (gs_get_stats) */
-    int32_t  reserved[7];
+    int32_t  tiles_per_wave;  /* consecutive 64-cycle tiles of one gate evaluated by one wave; 0 = 4 */
+    int32_t  reserved[6];
 } gs_options;
 
 /* Fills *opt with the defaults above. */

@@ -203,8 +203,9 @@ extern "C" gs_status gs_check_stimulus(int32_t n_inputs, int32_t period_ps, int3
 extern "C" void gs_default_options(gs_options *o)
 {
     std::memset(o, 0, sizeof(*o));
-    o->lds_cap = 16;
+    o->lds_cap = 8;
     o->waves_per_block = 4;
+    o->tiles_per_wave = 4;
     o->schedule = GS_SCHED_LEVELS;
 }
 
@@ -233,8 +234,10 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
     gs_options o;
     if (opt) o = *opt;
     else gs_default_options(&o);
-    if (o.lds_cap == 0) o.lds_cap = 16;
+    if (o.lds_cap == 0) o.lds_cap = 8;
     if (o.waves_per_block == 0) o.waves_per_block = 4;
+    if (o.tiles_per_wave == 0) o.tiles_per_wave = 4;
+    if (o.tiles_per_wave < 1 || o.tiles_per_wave > 64) return gs_fail(nullptr, GS_E_INVALID, "tiles_per_wave must be 1..64");
     if (o.lds_cap != 4 && o.lds_cap != 8 && o.lds_cap != 16 && o.lds_cap != 32)
         return gs_fail(nullptr, GS_E_INVALID, "lds_cap must be 4, 8, 16 or 32");
     if (o.waves_per_block < 1 || o.waves_per_block > 8) return gs_fail(nullptr, GS_E_INVALID, "waves_per_block must be 1..8");
@@ -727,6 +730,8 @@ static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t
     std::vector<Seg> segs(std::max(1, d->L));
     // stripe salt: each launch continues the round robin where the last one ended
     const uint32_t wpb = (uint32_t)ctx->opt.waves_per_block;
+    const uint32_t tpw = (uint32_t)ctx->opt.tiles_per_wave;
+    const uint64_t ngroup = ((uint64_t)tiles + tpw - 1) / tpw;
     uint64_t salt = ((uint64_t)d->I * tiles + 3) / 4;
     for (int32_t l = 1; l <= d->L; l++) {
         Seg &g = segs[l - 1];
@@ -739,7 +744,7 @@ static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t
         g.win = v;
         g.saif = stage;
         g.salt = (uint32_t)salt;
-        salt += ((uint64_t)g.n_gates * tiles + wpb - 1) / wpb;
+        salt += ((uint64_t)g.n_gates * ngroup + wpb - 1) / wpb * tpw;
     }
     if ((st = gs_ensure_segs(ctx, segs.size()))) return st;
     HIPCHK(hipMemcpyAsync(ctx->d_segs, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice, hs));
@@ -753,10 +758,10 @@ static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t
     HIPCHK(launch_expand(sv, v, stage, c0, 0u, hs));
     if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     for (int32_t l = 1; l <= d->L; l++) {
-        const uint64_t nw = (uint64_t)segs[l - 1].n_gates * tiles;
+        const uint64_t nw = (uint64_t)segs[l - 1].n_gates * ngroup;
         if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
         HIPCHK(launch_gate_eval(ctx->d_segs + (l - 1), 1, nw, d->has_wires ? 1 : 0, ctx->opt.lds_cap,
-                                ctx->opt.waves_per_block, d->level_kmax[l], hs));
+                                ctx->opt.waves_per_block, d->level_kmax[l], (uint32_t)ctx->opt.tiles_per_wave, hs));
         if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     }
     unsigned long long hflags[4];

@@ -108,6 +108,6 @@ hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n
 hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, uint32_t salt, hipStream_t s);
 
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires,
-                            int32_t cap, int32_t wpb, int32_t kmax, hipStream_t s);
+                            int32_t cap, int32_t wpb, int32_t kmax, uint32_t tpw, hipStream_t s);
 
 }  // namespace gs

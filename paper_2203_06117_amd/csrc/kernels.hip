@@ -9,24 +9,56 @@
 
 namespace gs {
 
+// Explicit global address space: pointers read out of the segment table
+// would otherwise stay generic and every access would become a flat
+// instruction that waits on both the vector-memory and the LDS counters.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GAS __attribute__((address_space(1)))
+#else
+#define GAS
+#endif
+
+template <typename T>
+__device__ __forceinline__ GAS T *glob(T *p)
+{
+    return (GAS T *)p;
+}
+
+
 // --------------------------------------------------------------------------
 // wave-level helpers
 // --------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+// Cross-lane data movement through DPP (no LDS round trip).  row_shr:n
+// shifts within each row of 16 lanes; row_bcast:15 / row_bcast:31 carry the
+// last lane of a row into the following rows.  Lanes without a source
+// (and rows masked off) receive 0.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v)
 {
-#pragma unroll
-    for (int d = 1; d < kLanes; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, kLanes);
-        if (lane >= d) v += o;
-    }
-    return v;
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, BANK_MASK, true);
 }
 
-__device__ __forceinline__ int32_t wave_sum(int32_t v)
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
-#pragma unroll
-    for (int d = kLanes / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kLanes);
-    return v;
+    x += dpp0<0x111>(x);             // row_shr:1
+    x += dpp0<0x112>(x);             // row_shr:2
+    x += dpp0<0x114>(x);             // row_shr:4
+    x += dpp0<0x118>(x);             // row_shr:8
+    x += dpp0<0x142, 0xa>(x);        // row_bcast:15 into rows 1 and 3
+    x += dpp0<0x143, 0xc>(x);        // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// Value of lane-1 in every lane (0 in lane 0): wave_shr:1.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t x)
+{
+    return dpp0<0x138>(x);
+}
+
+__device__ __forceinline__ int32_t lane63(uint32_t x)
+{
+    return __builtin_amdgcn_readlane((int)x, kLanes - 1);
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v)
@@ -49,26 +81,28 @@ __device__ __forceinline__ bool place_chunk(const WinView &win, uint64_t ci, uin
 {
     bool ok = true;
     if (total > kMaxChunk) {
-        if (lane == 0) atomicOr(&win.flags[1], 1u);
+        if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = false;
     }
     uint64_t b = 0;
     if (ok && total > 0) {
         const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
-        if (lane == 0) b = atomicAdd(win.bump + (size_t)stripe * kBumpStride, (unsigned long long)total);
+        if (lane == 0)
+            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)total,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         b = uniform64(b);
         if (b + total > win.slice_words) {
-            if (lane == 0) atomicOr(&win.flags[0], 1u);
+            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok = false;
         }
         b += (uint64_t)stripe * win.slice_words;
     }
-    win.ends[ci * kLanes + lane] = ok ? (uint16_t)incl : (uint16_t)0;
+    *glob(win.ends + ci * kLanes + lane) = ok ? (uint16_t)incl : (uint16_t)0;
     if (lane == 0) {
         ChunkHdr h;
         h.off = ok ? b : 0;
         h.mask = mask;
-        win.hdr[ci] = h;
+        *glob(win.hdr + ci) = h;
     }
     base = b;
     return ok;
@@ -233,8 +267,8 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     }
     const uint32_t cnt = (uint32_t)(e - s);
     const int v0 = active ? (int)((st.init[i] + (uint64_t)(s - lo)) & 1) : 0;
-    const uint32_t incl = wave_incl_scan(cnt, lane);
-    const uint32_t total = uniform(__shfl(incl, kLanes - 1, kLanes));
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t total = (uint32_t)lane63(incl);
     const uint64_t mask = __ballot(v0 != 0);
     const uint64_t ci = (uint64_t)i * ntile + tile;
     uint64_t base;
@@ -243,17 +277,19 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     int v = v0, a = 0;
     for (uint32_t j = 0; j < cnt; j++) {
         int32_t tl = (int32_t)(st.toggle_ps[s + j] - c0);
-        if (ok) win.times[base + (incl - cnt) + j] = tl;
+        if (ok) *glob(win.times + base + (incl - cnt) + j) = tl;
         v ^= 1;
         a += v ? -tl : tl;
     }
     const int32_t t1 = active ? v * (int32_t)T + a : 0;
-    const int32_t sum1 = wave_sum(t1);
+    const int32_t sum1 = lane63(wave_incl_scan((uint32_t)t1));
     const uint32_t nact = (uint32_t)__popcll(__ballot(active));
     if (lane == 0) {
-        atomicAdd(&acc.tc[i], (unsigned long long)total);
-        atomicAdd(&acc.t1[i], (unsigned long long)(int64_t)sum1);
-        atomicAdd(&acc.t0[i], (unsigned long long)((int64_t)nact * T - sum1));
+        __hip_atomic_fetch_add(glob(acc.tc + i), (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(glob(acc.t1 + i), (unsigned long long)(int64_t)sum1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(glob(acc.t0 + i), (unsigned long long)((int64_t)nact * T - sum1), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -288,8 +324,19 @@ hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, 
 // place in global memory.  SAIF counts of the output net are reduced over
 // the wave and added with one atomic each.
 // --------------------------------------------------------------------------
+extern __shared__ int32_t gs_lds[];
+
+// chunk[idx] with a 32-bit byte offset from a wave-uniform base, so the
+// load can use the scalar-base + vector-offset addressing mode
+__device__ __forceinline__ int32_t ld_word(const int32_t *chunk, uint32_t idx)
+{
+    return *(const GAS int32_t *)((const GAS char *)glob(chunk) + (uint64_t)(idx << 2));
+}
+
+// Per-lane walk state of one gate over one cycle; the per-pin arc data are
+// wave-uniform.
 template <int K, bool WIRES>
-struct Lane {
+struct Pins {
     const int32_t *chunk[K];
     uint32_t idx[K], end[K];
     int32_t a[K];
@@ -299,7 +346,7 @@ struct Lane {
     __device__ __forceinline__ void advance(int j)
     {
         if (!WIRES) {
-            a[j] = idx[j] < end[j] ? chunk[j][idx[j]] : kInf;
+            a[j] = idx[j] < end[j] ? ld_word(chunk[j], idx[j]) : kInf;
             return;
         }
         const int pv = (state >> j) & 1;
@@ -308,9 +355,9 @@ struct Lane {
                 a[j] = kInf;
                 return;
             }
-            const int32_t e0 = chunk[j][idx[j]];
+            const int32_t e0 = ld_word(chunk[j], idx[j]);
             const int32_t d = pv ? wf[j] : wr[j];       // the net edge goes to !pv
-            if (idx[j] + 1 < end[j] && chunk[j][idx[j] + 1] - e0 < d) {
+            if (idx[j] + 1 < end[j] && ld_word(chunk[j], idx[j] + 1) - e0 < d) {
                 idx[j] += 2;                            // pulse narrower than the wire delay
                 continue;
             }
@@ -318,47 +365,89 @@ struct Lane {
             return;
         }
     }
+
+    // Smallest arc delay over the pins in sw for output value y, in the
+    // current pin state (gates with more than three pins; smaller gates
+    // read it from the wave's lookup table).
+    __device__ __forceinline__ int32_t delay(uint32_t sw, int y) const
+    {
+        int32_t d = kInf;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            // arithmetic selects: a select between array elements would
+            // become an address select and force the arrays to scratch
+            const int32_t sel = -(int32_t)((state >> q[j]) & 1);
+            const int32_t rise = r0[j] + (sel & (r1[j] - r0[j]));
+            const int32_t fall = f0[j] + (sel & (f1[j] - f0[j]));
+            const int32_t dj = fall + ((-y) & (rise - fall));
+            const int32_t m = -(int32_t)((sw >> j) & 1);
+            d = min(d, (dj & m) | (kInf & ~m));
+        }
+        return d;
+    }
 };
 
-// MODE 0: stage into LDS (at most CAP entries per lane).  MODE 1: write to
-// global memory at dst[0 .. keep) (entries at or beyond `keep` are retracted
+// Lookup table of a gate with up to three pins, one entry per (pin state
+// after an event, mask of the pins that switched): bit 0 = the truth-table
+// output, bits 1.. = the smallest arc delay of the switched pins for that
+// output edge.  64 words per wave in LDS, built by the 64 lanes at once.
+template <int K, bool WIRES>
+__device__ __forceinline__ void build_lut(const Pins<K, WIRES> &P, uint64_t truth, int lane, uint32_t lut_base)
+{
+    const uint32_t st = (uint32_t)lane >> 3, m = (uint32_t)lane & 7u;
+    const int y = (int)((truth >> st) & 1);
+    int32_t d = kInf >> 1;
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+        const int32_t sel = -(int32_t)((st >> P.q[j]) & 1);
+        const int32_t rise = P.r0[j] + (sel & (P.r1[j] - P.r0[j]));
+        const int32_t fall = P.f0[j] + (sel & (P.f1[j] - P.f0[j]));
+        const int32_t dj = fall + ((-y) & (rise - fall));
+        const int32_t mj = -(int32_t)((m >> j) & 1);
+        d = min(d, (dj & mj) | ((kInf >> 1) & ~mj));
+    }
+    gs_lds[lut_base + lane] = (d << 1) | y;
+}
+
+// One walk over a lane's fanin lists (Algorithm 1's event loop).  MODE 0
+// stages output edges in LDS (at most CAP per lane); MODE 1 writes them to
+// dst[0 .. keep) in global memory (entries at or beyond `keep` are retracted
 // before the walk ends, so they are not stored).
 template <int K, bool WIRES, int MODE, int CAP>
-__device__ __forceinline__ void walk(Lane<K, WIRES> &L, uint64_t truth, int32_t T, int z, int32_t *lds_lane,
-                                     int32_t *dst, int32_t keep, int32_t &cnt_out, int32_t &acc_out, int32_t &z_out)
+__device__ __forceinline__ void walk(Pins<K, WIRES> &P, uint64_t truth, int32_t T, int z, uint32_t lut_base,
+                                     uint32_t out_lane, int32_t *dst, int32_t keep, int32_t &cnt_out,
+                                     int32_t &acc_out, int32_t &z_out)
 {
 #pragma unroll
-    for (int j = 0; j < K; j++) L.advance(j);
+    for (int j = 0; j < K; j++) P.advance(j);
     int32_t W = 0, Wp = 0, cnt = 0, acc = 0;
     for (;;) {
-        int32_t t = L.a[0];
+        int32_t t = P.a[0];
 #pragma unroll
-        for (int j = 1; j < K; j++) t = min(t, L.a[j]);
+        for (int j = 1; j < K; j++) t = min(t, P.a[j]);
         if (t == kInf) break;
         uint32_t sw = 0;
 #pragma unroll
         for (int j = 0; j < K; j++) {
-            if (L.a[j] == t) {
+            if (P.a[j] == t) {
                 sw |= 1u << j;
-                L.state ^= 1u << j;
-                L.idx[j]++;
-                L.advance(j);
+                P.state ^= 1u << j;             // the wire filter reads the pin's new value
+                P.idx[j]++;
+                P.advance(j);
             }
         }
-        const int y = (int)((truth >> L.state) & 1);
+        int y;
+        int32_t d;
+        if (K <= 3) {
+            const int32_t ent = gs_lds[lut_base + ((P.state << 3) | sw)];
+            y = ent & 1;
+            d = ent >> 1;
+        } else {
+            y = (int)((truth >> P.state) & 1);
+            d = 0;
+        }
         if (y != z) {
-            int32_t d = kInf;
-#pragma unroll
-            for (int j = 0; j < K; j++) {
-                // arithmetic selects: a select between array elements would
-                // become an address select and force the arrays to scratch
-                const int32_t sel = -(int32_t)((L.state >> L.q[j]) & 1);
-                const int32_t rise = L.r0[j] + (sel & (L.r1[j] - L.r0[j]));
-                const int32_t fall = L.f0[j] + (sel & (L.f1[j] - L.f0[j]));
-                const int32_t dj = fall + ((-y) & (rise - fall));
-                const int32_t m = -(int32_t)((sw >> j) & 1);      // pin j switched at t
-                d = min(d, (dj & m) | (kInf & ~m));
-            }
+            if (K > 3) d = P.delay(sw, y);
             const bool retract = t < W;
             const int32_t e = retract ? W : t + d;
             const int32_t ce = min(e, T);
@@ -368,9 +457,9 @@ __device__ __forceinline__ void walk(Lane<K, WIRES> &L, uint64_t truth, int32_t 
                 W = Wp;
             } else {
                 if (MODE == 0) {
-                    if (cnt < CAP) lds_lane[cnt * kLanes] = t + d;
+                    if (cnt < CAP) gs_lds[out_lane + cnt * kLanes] = t + d;
                 } else {
-                    if (cnt < keep) dst[cnt] = t + d;
+                    if (cnt < keep) *glob(dst + cnt) = t + d;
                 }
                 cnt++;
                 Wp = W;
@@ -384,74 +473,98 @@ __device__ __forceinline__ void walk(Lane<K, WIRES> &L, uint64_t truth, int32_t 
     z_out = z;
 }
 
+// One gate over `ntl` consecutive tiles starting at tile0 (one lane per
+// cycle of a tile).  The per-gate work (arc data, delay table) is done once;
+// SAIF counts of the output net are summed over the tiles and added with one
+// atomic per counter.
 template <int K, bool WIRES, int CAP>
-__device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint32_t tile, int lane, int32_t *lds)
+__device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint32_t tile0, uint32_t ntl, int lane,
+                                          uint32_t lut_base, uint32_t out_base)
 {
     const WinView &win = sg.win;
-    const int32_t lc = (int32_t)(tile * kLanes) + lane;
-    const bool active = lc < win.n_cycles;
     const int32_t T = win.period;
-    Lane<K, WIRES> L;
-    uint32_t idx0[K];
-    L.state = 0;
+    const uint32_t ntile = (uint32_t)win.n_tiles;
+    Pins<K, WIRES> P;
+    int32_t net[K];
 #pragma unroll
     for (int j = 0; j < K; j++) {
-        const PinRec pr = sg.pins[g.pin0 + j];
-        const uint64_t ci = (uint64_t)(uint32_t)pr.net * (uint32_t)win.n_tiles + tile;
-        const ChunkHdr h = win.hdr[ci];
-        const uint16_t *e = win.ends + ci * kLanes;
-        const uint32_t hi = e[lane];
-        const uint32_t lo = lane > 0 ? e[lane - 1] : 0u;
-        L.chunk[j] = win.times + h.off;
-        L.idx[j] = active ? lo : 0u;
-        L.end[j] = active ? hi : 0u;
-        idx0[j] = L.idx[j];
-        L.state |= (uint32_t)((h.mask >> lane) & 1) << j;
-        L.q[j] = pr.q;
-        L.r0[j] = pr.r0;
-        L.f0[j] = pr.f0;
-        L.r1[j] = pr.r1;
-        L.f1[j] = pr.f1;
-        L.wr[j] = pr.wr;
-        L.wf[j] = pr.wf;
+        const PinRec pr = *glob(sg.pins + g.pin0 + j);
+        net[j] = pr.net;
+        P.q[j] = pr.q; P.r0[j] = pr.r0; P.f0[j] = pr.f0; P.r1[j] = pr.r1; P.f1[j] = pr.f1;
+        P.wr[j] = pr.wr; P.wf[j] = pr.wf;
     }
-    const uint32_t state0 = L.state;
-    const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
-
-    int32_t cnt, acc, z;
-    walk<K, WIRES, 0, CAP>(L, g.truth, T, y0, lds + lane, nullptr, 0, cnt, acc, z);
-
-    const uint32_t ucnt = (uint32_t)cnt;
-    const uint32_t incl = wave_incl_scan(ucnt, lane);
-    const uint32_t total = uniform(__shfl(incl, kLanes - 1, kLanes));
-    const uint64_t mask = __ballot(active && y0);
-    const uint64_t ci = (uint64_t)g.out * (uint32_t)win.n_tiles + tile;
-    uint64_t base;
-    const bool ok = place_chunk(win, ci, incl, total, mask, lane, sg.salt, base);
-    const uint32_t excl = incl - ucnt;
-    if (ok) {
-        int32_t *out = win.times + base + excl;
-        const int32_t n = cnt < CAP ? cnt : CAP;
-        for (int32_t i = 0; i < n; i++) out[i] = lds[lane + i * kLanes];
-        const uint64_t spill = __ballot(cnt > CAP);
-        if (spill) {
-            if (cnt > CAP) {
+    if (K <= 3) {
+        build_lut<K, WIRES>(P, g.truth, lane, lut_base);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const uint32_t out_lane = out_base + lane;
+    uint32_t tc_sum = 0, nact_sum = 0;
+    int32_t t1_lane = 0;
+    for (uint32_t tt = 0; tt < ntl; tt++) {
+        const uint32_t tile = tile0 + tt;
+        const int32_t lc = (int32_t)(tile * kLanes) + lane;
+        const bool active = lc < win.n_cycles;
+        uint32_t idx0[K];
+        uint32_t state0 = 0;
 #pragma unroll
-                for (int j = 0; j < K; j++) L.idx[j] = idx0[j];
-                L.state = state0;
-                int32_t c2, a2, z2;
-                walk<K, WIRES, 1, CAP>(L, g.truth, T, y0, nullptr, out, cnt, c2, a2, z2);
-            }
-            if (lane == 0) atomicAdd(&win.flags[2], (unsigned int)__popcll(spill));
+        for (int j = 0; j < K; j++) {
+            const uint64_t ci = (uint64_t)(uint32_t)net[j] * ntile + tile;
+            // the chunk header is wave-uniform: one load, moved to scalar registers
+            const ChunkHdr hv = *glob(win.hdr + ci);
+            ChunkHdr h;
+            h.off = uniform64(hv.off);
+            h.mask = uniform64(hv.mask);
+            const uint32_t e = *glob(win.ends + ci * kLanes + lane);
+            const uint32_t lo = wave_shr1(e);
+            P.chunk[j] = win.times + h.off;
+            P.idx[j] = idx0[j] = active ? lo : 0u;
+            P.end[j] = active ? e : 0u;
+            state0 |= (uint32_t)((h.mask >> lane) & 1) << j;
         }
+        P.state = state0;
+        const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
+        int32_t cnt, acc, z;
+        walk<K, WIRES, 0, CAP>(P, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
+
+        const uint32_t ucnt = (uint32_t)cnt;
+        const uint32_t incl = wave_incl_scan(ucnt);
+        const uint32_t total = (uint32_t)lane63(incl);
+        const uint64_t mask = __ballot(active && y0);
+        const uint64_t ci = (uint64_t)g.out * ntile + tile;
+        uint64_t base;
+        const bool ok = place_chunk(win, ci, incl, total, mask, lane, sg.salt + tt, base);
+        if (ok) {
+            int32_t *out = win.times + base + (incl - ucnt);
+            const int32_t n = cnt < CAP ? cnt : CAP;
+            for (int32_t i = 0; i < n; i++) *glob(out + i) = gs_lds[out_lane + i * kLanes];
+            const uint64_t spill = __ballot(cnt > CAP);
+            if (spill) {
+                if (cnt > CAP) {
+#pragma unroll
+                    for (int j = 0; j < K; j++) P.idx[j] = idx0[j];
+                    P.state = state0;
+                    int32_t c2, a2, z2;
+                    walk<K, WIRES, 1, CAP>(P, g.truth, T, y0, lut_base, 0, out, cnt, c2, a2, z2);
+                }
+                if (lane == 0)
+                    __hip_atomic_fetch_add(glob(win.flags + 2), (unsigned int)__popcll(spill), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        tc_sum += total;
+        nact_sum += (uint32_t)__popcll(__ballot(active));
+        t1_lane += active ? z * T + acc : 0;
     }
-    const int32_t t1 = active ? z * T + acc : 0;
-    const int32_t sum1 = wave_sum(t1);
-    const uint32_t nact = (uint32_t)__popcll(__ballot(active));
+    const int32_t sum1 = lane63(wave_incl_scan((uint32_t)t1_lane));
     if (lane == 0) {
-        atomicAdd(&sg.saif.tc[g.out], (unsigned long long)total);
-        atomicAdd(&sg.saif.t1[g.out], (unsigned long long)(int64_t)sum1);
-        atomicAdd(&sg.saif.t0[g.out], (unsigned long long)((int64_t)nact * T - sum1));
+        __hip_atomic_fetch_add(glob(sg.saif.tc + g.out), (unsigned long long)tc_sum, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(glob(sg.saif.t1 + g.out), (unsigned long long)(int64_t)sum1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(glob(sg.saif.t0 + g.out), (unsigned long long)((int64_t)nact_sum * T - sum1),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -466,10 +579,12 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int n, uin
     return lo;
 }
 
+// Wave w of a launch -> (segment, gate, group of tpw consecutive tiles).
+// LDS per wave: 64 words of delay table, then CAP x 64 staged output words.
 template <bool WIRES, int CAP, int KMAX>
-__global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ segs, int32_t n_segs, uint64_t n_waves)
+__global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ segs, int32_t n_segs, uint64_t n_waves,
+                                                        uint32_t tpw)
 {
-    extern __shared__ int32_t lds_all[];
     const int lane = threadIdx.x & (kLanes - 1);
     const uint32_t wpb = blockDim.x / kLanes;
     const uint32_t wib = uniform(threadIdx.x / kLanes);
@@ -479,47 +594,52 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const Seg &sg = segs[si];
     const uint32_t local = (uint32_t)(w - sg.wave_begin);
     const uint32_t ntile = (uint32_t)sg.win.n_tiles;
-    const uint32_t gi = local / ntile;
-    const uint32_t tile = local - gi * ntile;
-    const GateRec g = sg.gates[sg.gate_begin + gi];
-    int32_t *lds = lds_all + (size_t)wib * CAP * kLanes;
+    const uint32_t ngroup = (ntile + tpw - 1) / tpw;
+    const uint32_t gi = local / ngroup;
+    const uint32_t grp = local - gi * ngroup;
+    const uint32_t tile0 = grp * tpw;
+    const uint32_t ntl = min(tpw, ntile - tile0);
+    const GateRec g = *glob(sg.gates + sg.gate_begin + gi);
+    const uint32_t lut_base = wib * (kLanes + CAP * kLanes);
+    const uint32_t out_base = lut_base + kLanes;
     switch (g.k) {
-    case 1: eval_gate<1, WIRES, CAP>(sg, g, tile, lane, lds); break;
-    case 2: eval_gate<2, WIRES, CAP>(sg, g, tile, lane, lds); break;
-    case 3: eval_gate<3, WIRES, CAP>(sg, g, tile, lane, lds); break;
-    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP>(sg, g, tile, lane, lds); break;
-    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP>(sg, g, tile, lane, lds); break;
-    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP>(sg, g, tile, lane, lds); break;
+    case 1: eval_gate<1, WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 2: eval_gate<2, WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 3: eval_gate<3, WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
     default: break;
     }
 }
 
 template <bool WIRES, int KMAX>
-static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t cap, int32_t wpb, hipStream_t s)
+static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t cap, int32_t wpb, uint32_t tpw,
+                            hipStream_t s)
 {
     const uint64_t blocks = (n_waves + wpb - 1) / wpb;
-    const size_t lds = (size_t)wpb * cap * kLanes * sizeof(int32_t);
+    const size_t lds = (size_t)wpb * ((size_t)cap * kLanes + kLanes) * sizeof(int32_t);
     const dim3 grid((unsigned)blocks), block(kLanes * wpb);
     switch (cap) {
-    case 4: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 4, KMAX>), grid, block, lds, s, segs, n_segs, n_waves); break;
-    case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX>), grid, block, lds, s, segs, n_segs, n_waves); break;
-    case 16: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 16, KMAX>), grid, block, lds, s, segs, n_segs, n_waves); break;
-    case 32: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 32, KMAX>), grid, block, lds, s, segs, n_segs, n_waves); break;
+    case 4: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 4, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 16: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 16, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 32: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 32, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires, int32_t cap,
-                            int32_t wpb, int32_t kmax, hipStream_t s)
+                            int32_t wpb, int32_t kmax, uint32_t tpw, hipStream_t s)
 {
     if (n_waves == 0) return hipSuccess;
-    if (wpb < 1 || wpb > 8) return hipErrorInvalidValue;
+    if (wpb < 1 || wpb > 8 || tpw < 1) return hipErrorInvalidValue;
     if (kmax <= 3)
-        return wires ? launch_ge<true, 3>(segs, n_segs, n_waves, cap, wpb, s)
-                     : launch_ge<false, 3>(segs, n_segs, n_waves, cap, wpb, s);
-    return wires ? launch_ge<true, 6>(segs, n_segs, n_waves, cap, wpb, s)
-                 : launch_ge<false, 6>(segs, n_segs, n_waves, cap, wpb, s);
+        return wires ? launch_ge<true, 3>(segs, n_segs, n_waves, cap, wpb, tpw, s)
+                     : launch_ge<false, 3>(segs, n_segs, n_waves, cap, wpb, tpw, s);
+    return wires ? launch_ge<true, 6>(segs, n_segs, n_waves, cap, wpb, tpw, s)
+                 : launch_ge<false, 6>(segs, n_segs, n_waves, cap, wpb, tpw, s);
 }
 
 }  // namespace gs

@@ -33,7 +33,7 @@ class Options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("hbm_budget", C.c_uint64),
                 ("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("window_cycles", C.c_int32),
                 ("lds_cap", C.c_int32), ("waves_per_block", C.c_int32), ("schedule", C.c_int32),
-                ("timing", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("timing", C.c_int32), ("tiles_per_wave", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class DesignInfo(C.Structure):
@@ -162,8 +162,8 @@ class GateSim:
     """One library context on one GPU."""
 
     def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0, arena=None,
-                 window_cycles: int = 0, lds_cap: int = 16, waves_per_block: int = 4,
-                 schedule: int = SCHED_LEVELS, timing: bool = False):
+                 window_cycles: int = 0, lds_cap: int = 0, waves_per_block: int = 4,
+                 schedule: int = SCHED_LEVELS, timing: bool = False, tiles_per_wave: int = 0):
         o = Options()
         _lib.gs_default_options(C.byref(o))
         o.device = device
@@ -178,6 +178,7 @@ class GateSim:
         o.waves_per_block = waves_per_block
         o.schedule = schedule
         o.timing = 1 if timing else 0
+        o.tiles_per_wave = tiles_per_wave
         h = P()
         st = _lib.gs_create(C.byref(o), C.byref(h))
         if st != GS_OK:
