@@ -83,7 +83,9 @@ typedef struct {
     int32_t  schedule;        /* GS_SCHED_LEVELS or GS_SCHED_GRAPH */
     int32_t  timing;          /* nonzero: time every gate-evaluation launch with HIP events (gs_get_stats) */
     int32_t  tiles_per_wave;  /* consecutive 64-cycle tiles of one gate evaluated by one wave; 0 = 4 */
-    int32_t  reserved[6];
+    int32_t  autotune;        /* nonzero: gs_simulate_batch picks lds_cap, waves_per_block and tiles_per_wave by
+                                 timing candidates on its largest job (once per batch shape) */
+    int32_t  reserved[5];
 } gs_options;
 
 /* Fills *opt with the defaults above. */
@@ -194,7 +196,8 @@ typedef struct {
     int64_t  gate_cycles;       /* gates x cycles simulated */
     int64_t  spilled_lanes;     /* (net, cycle) lists longer than the on-chip staging cap */
     int64_t  arena_words;       /* 32-bit transition slots used by the last window */
-    int64_t  reserved[6];
+    int64_t  graph_launches;    /* rounds replayed from a captured HIP graph */
+    int64_t  reserved[5];
 } gs_stats;
 
 gs_status gs_get_stats(gs_ctx *ctx, gs_stats *st, int32_t reset);
@@ -226,6 +229,18 @@ typedef struct {
 } gs_job;
 
 gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job *jobs);
+
+/* Autotuner: times candidate (lds_cap, waves_per_block, tiles_per_wave)
+ * settings of the gate-evaluation kernel on cycles [cycle_begin, cycle_end)
+ * (at most 4096) of (design, stim), with nothing added to the SAIF
+ * accumulators, and keeps the fastest in the context's options. */
+typedef struct {
+    int32_t lds_cap, waves_per_block, tiles_per_wave, reserved;
+    double  trial_ms;           /* gate-evaluation time of the winning setting on the trial */
+} gs_tuning;
+
+gs_status gs_autotune(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end,
+                      gs_tuning *out);
 
 /* ---------------------------------------------------------------------
  * Serving: a resident request loop with continuous batching (the

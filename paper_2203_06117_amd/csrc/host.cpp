@@ -263,6 +263,11 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
         }
         ctx->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return gs_fail(nullptr, GS_E_DEVICE, "hipStreamCreate failed");
+    }
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
         (void)hipGetLastError();
@@ -307,7 +312,9 @@ extern "C" gs_status gs_destroy(gs_ctx *ctx)
     gs_dev_free(ctx->d_misc);
     gs_dev_free(ctx->d_bump);
     for (auto &ev : ctx->events) (void)hipEventDestroy(ev);
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    gs_graph_cache_clear(ctx);
+    gs_dev_free(ctx->d_c0);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return GS_OK;
@@ -331,7 +338,7 @@ extern "C" gs_status gs_load_cells(gs_ctx *ctx, int32_t n_cells, const uint8_t *
     return GS_OK;
 }
 
-static Design *get_design(gs_ctx *ctx, int32_t id)
+Design *gs_get_design(gs_ctx *ctx, int32_t id)
 {
     if (id < 0 || id >= (int32_t)ctx->designs.size()) return nullptr;
     return ctx->designs[id];
@@ -493,7 +500,7 @@ static gs_status pack_design(gs_ctx *ctx, Design *d)
 extern "C" gs_status gs_load_arcs(gs_ctx *ctx, int32_t design, int64_t n_arcs, const gs_arc *arcs)
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
-    Design *d = get_design(ctx, design);
+    Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     std::vector<int32_t> q, r0, f0, r1, f1;
     int32_t mx, zd;
@@ -511,7 +518,7 @@ extern "C" gs_status gs_load_arcs(gs_ctx *ctx, int32_t design, int64_t n_arcs, c
 extern "C" gs_status gs_load_wires(gs_ctx *ctx, int32_t design, const int32_t *rise_ps, const int32_t *fall_ps)
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
-    Design *d = get_design(ctx, design);
+    Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     if ((rise_ps == nullptr) != (fall_ps == nullptr)) return gs_fail(ctx, GS_E_INVALID, "give both wire arrays or neither");
     std::vector<int32_t> wr(d->F, 0), wf(d->F, 0);
@@ -545,7 +552,7 @@ extern "C" gs_status gs_load_stimulus(gs_ctx *ctx, int32_t design, int32_t perio
                                       int32_t *stim_id)
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
-    Design *d = get_design(ctx, design);
+    Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     gs_status st = check_stim_impl(ctx, d->I, period_ps, n_cycles, init, toggle_ptr, toggle_ps);
     if (st) return st;
@@ -712,148 +719,10 @@ hipEvent_t gs_event(gs_ctx *ctx, size_t i)
     return ctx->events[i];
 }
 
-// Simulates one window [c0, c0 + cycles) of (d, s); on success the SAIF
-// counts are committed to the design.  *retry is set when the transition
-// arena filled up (nothing committed).
-static gs_status run_window(gs_ctx *ctx, Design *d, Stim *s, int32_t c0, int32_t cycles, uint64_t arena_words,
-                            bool *retry)
-{
-    hipStream_t hs = ctx->stream;
-    *retry = false;
-    const int32_t tiles = (cycles + kLanes - 1) / kLanes;
-    const uint64_t n_chunks = (uint64_t)d->N * tiles;
-    gs_status st = gs_window_reserve(ctx, &ctx->win, n_chunks, arena_words);
-    if (st) return st;
-    WinView v = gs_make_view(ctx, ctx->win, cycles, s->period, 0, n_chunks);
-    SaifAcc stage{d->d_stage, d->d_stage + d->N, d->d_stage + 2 * (size_t)d->N};
-    // segment table: one per level
-    std::vector<Seg> segs(std::max(1, d->L));
-    // stripe salt: each launch continues the round robin where the last one ended
-    const uint32_t wpb = (uint32_t)ctx->opt.waves_per_block;
-    const uint32_t tpw = (uint32_t)ctx->opt.tiles_per_wave;
-    const uint64_t ngroup = ((uint64_t)tiles + tpw - 1) / tpw;
-    uint64_t salt = ((uint64_t)d->I * tiles + 3) / 4;
-    for (int32_t l = 1; l <= d->L; l++) {
-        Seg &g = segs[l - 1];
-        std::memset(&g, 0, sizeof(g));
-        g.wave_begin = 0;
-        g.gates = d->d_gates;
-        g.pins = d->d_pins;
-        g.gate_begin = d->level_ptr[l];
-        g.n_gates = d->level_ptr[l + 1] - d->level_ptr[l];
-        g.win = v;
-        g.saif = stage;
-        g.salt = (uint32_t)salt;
-        salt += ((uint64_t)g.n_gates * ngroup + wpb - 1) / wpb * tpw;
-    }
-    if ((st = gs_ensure_segs(ctx, segs.size()))) return st;
-    HIPCHK(hipMemcpyAsync(ctx->d_segs, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice, hs));
-    HIPCHK(launch_fill_u64(ctx->d_misc, 4, 0ull, hs));                   // flags
-    HIPCHK(launch_fill_u64(ctx->d_bump, (uint64_t)kMaxStripes * kBumpStride, 0ull, hs));
-    HIPCHK(launch_fill_u64(d->d_stage, 3 * (uint64_t)d->N, 0ull, hs));
-    const bool timing = ctx->opt.timing != 0;
-    size_t ev = 0;
-    if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
-    StimView sv{s->d_init, s->d_tp, s->d_ts, d->I, s->period};
-    HIPCHK(launch_expand(sv, v, stage, c0, 0u, hs));
-    if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
-    for (int32_t l = 1; l <= d->L; l++) {
-        const uint64_t nw = (uint64_t)segs[l - 1].n_gates * ngroup;
-        if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
-        HIPCHK(launch_gate_eval(ctx->d_segs + (l - 1), 1, nw, d->has_wires ? 1 : 0, ctx->opt.lds_cap,
-                                ctx->opt.waves_per_block, d->level_kmax[l], (uint32_t)ctx->opt.tiles_per_wave, hs));
-        if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
-    }
-    unsigned long long hflags[4];
-    std::vector<unsigned long long> hb((size_t)kMaxStripes * kBumpStride);
-    HIPCHK(hipMemcpyAsync(hflags, ctx->d_misc, sizeof(hflags), hipMemcpyDeviceToHost, hs));
-    HIPCHK(hipMemcpyAsync(hb.data(), ctx->d_bump, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost, hs));
-    HIPCHK(hipStreamSynchronize(hs));
-    uint64_t used = 0;
-    for (uint32_t i = 0; i <= v.stripe_mask; i++) used += std::min<uint64_t>(hb[(size_t)i * kBumpStride], v.slice_words);
-    const unsigned int *f32 = (const unsigned int *)(hflags + 1);
-    if (timing) {
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
-        ctx->stats.expand_ms += ms;
-        for (int32_t l = 0; l < d->L; l++) {
-            HIPCHK(hipEventElapsedTime(&ms, ctx->events[2 + 2 * l], ctx->events[3 + 2 * l]));
-            ctx->stats.gate_eval_ms += ms;
-        }
-    }
-    ctx->stats.gate_eval_launches += d->L;
-    ctx->stats.spilled_lanes += f32[2];
-    ctx->stats.arena_words = (int64_t)used;
-    if (f32[1]) return gs_fail(ctx, GS_E_CAPACITY, "more than %u transitions in one (net, 64-cycle tile)", kMaxChunk);
-    if (f32[0]) {
-        *retry = true;
-        ctx->stats.window_retries++;
-        return GS_OK;
-    }
-    HIPCHK(launch_add_u64(d->d_saif, d->d_stage, 3 * (uint64_t)d->N, hs));
-    ctx->stats.windows++;
-    ctx->stats.gate_cycles += (int64_t)d->G * cycles;
-    ctx->last.design = (int32_t)(std::find(ctx->designs.begin(), ctx->designs.end(), d) - ctx->designs.begin());
-    ctx->last.stim = (int32_t)(std::find(ctx->stims.begin(), ctx->stims.end(), s) - ctx->stims.begin());
-    ctx->last.c0 = c0;
-    ctx->last.cycles = cycles;
-    ctx->last.chunk_base = 0;
-    ctx->last.n_nets = d->N;
-    return GS_OK;
-}
-
-extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end)
-{
-    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
-    if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
-    Design *d = get_design(ctx, design);
-    if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
-    if (stim < 0 || stim >= (int32_t)ctx->stims.size() || !ctx->stims[stim] || ctx->stims[stim]->design != design)
-        return gs_fail(ctx, GS_E_INVALID, "stimulus %d does not belong to design %d", stim, design);
-    Stim *s = ctx->stims[stim];
-    gs_status st = gs_check_ranges(ctx, d, s, cycle_begin, cycle_end);
-    if (st) return st;
-    (void)hipSetDevice(ctx->opt.device);
-    const uint64_t t_start = gs_now_ns();
-    ctx->last = LastWindow();
-    int32_t W = ctx->opt.window_cycles;
-    if (W <= 0) {
-        W = 4096;
-        while (W > kLanes && gs_header_bytes(d->N, W) * 3 > ctx->budget) W /= 2;
-    }
-    int32_t c0 = cycle_begin;
-    uint64_t grown = 0;                     // arena words requested after a retry
-    while (c0 < cycle_end) {
-        const int32_t cyc = std::min(W, cycle_end - c0);
-        const uint64_t hb = gs_header_bytes(d->N, cyc);
-        if (hb >= ctx->budget) return gs_fail(ctx, GS_E_NOMEM, "budget cannot hold one window's headers");
-        const uint64_t max_words = (ctx->budget - hb) / sizeof(int32_t);
-        uint64_t words = gs_arena_guess(d->N, cyc, s->tog_prefix[c0 + cyc] - s->tog_prefix[c0]);
-        words = std::max(words, std::max<uint64_t>(grown, ctx->win.words));
-        words = std::min(words, max_words);
-        bool retry = false;
-        st = run_window(ctx, d, s, c0, cyc, words, &retry);
-        if (st) return st;
-        if (retry) {
-            if (words < max_words) {
-                grown = std::min(max_words, words * 2);
-            } else if (W > kLanes) {
-                W = std::max(kLanes, W / 2);
-            } else {
-                return gs_fail(ctx, GS_E_NOMEM, "transitions of one 64-cycle window exceed the memory budget");
-            }
-            continue;
-        }
-        c0 += cyc;
-    }
-    ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
-    return GS_OK;
-}
-
 extern "C" gs_status gs_read_saif(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0, int64_t *t1, int32_t reset)
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
-    Design *d = get_design(ctx, design);
+    Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     (void)hipSetDevice(ctx->opt.device);
     hipStream_t hs = ctx->stream;
@@ -872,7 +741,7 @@ extern "C" gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim,
                                       int32_t *init, int32_t *times, int32_t cap, int32_t *n)
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
-    Design *d = get_design(ctx, design);
+    Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     if (net < 0 || net >= d->N) return gs_fail(ctx, GS_E_INVALID, "net %d out of range", net);
     const LastWindow &lw = ctx->last;
@@ -902,7 +771,7 @@ extern "C" gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim,
 extern "C" gs_status gs_get_design_info(gs_ctx *ctx, int32_t design, gs_design_info *info)
 {
     if (!ctx || !info) return gs_fail(ctx, GS_E_INVALID, "null argument");
-    Design *d = get_design(ctx, design);
+    Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     std::memset(info, 0, sizeof(*info));
     info->n_inputs = d->I;
@@ -919,7 +788,7 @@ extern "C" gs_status gs_get_design_info(gs_ctx *ctx, int32_t design, gs_design_i
 extern "C" gs_status gs_get_levels(gs_ctx *ctx, int32_t design, int32_t *level)
 {
     if (!ctx || !level) return gs_fail(ctx, GS_E_INVALID, "null argument");
-    Design *d = get_design(ctx, design);
+    Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     std::memcpy(level, d->level.data(), sizeof(int32_t) * d->G);
     return GS_OK;

@@ -4,6 +4,7 @@
 #include "gatesim.h"
 #include "internal.h"
 
+#include <array>
 #include <atomic>
 #include <condition_variable>
 #include <deque>
@@ -66,6 +67,11 @@ struct LastWindow {
 
 struct ServeState;
 
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    gs::Seg *segs = nullptr;                 // the graph's own segment table
+};
+
 struct gs_ctx {
     gs_options opt;
     hipStream_t stream = nullptr;
@@ -84,9 +90,12 @@ struct gs_ctx {
     unsigned long long *d_bump = nullptr;    // kMaxStripes stripe counters, kBumpStride apart
     std::vector<hipEvent_t> events;
     gs_stats stats{};
-    hipGraphExec_t graph_exec = nullptr;
-    // batching: cached graph key
-    std::vector<int64_t> graph_key;
+    // captured rounds, keyed by everything their launches depend on
+    std::map<std::string, GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;        // library stream that graphs are captured on and launched from
+    int32_t *d_c0 = nullptr;                 // first cycle of every piece of the running round
+    size_t c0_cap = 0;
+    std::map<std::string, std::array<int32_t, 3>> tuned;   // autotuned (cap, wpb, tpw) per batch shape
     // serving
     ServeState *serve = nullptr;
     bool serving = false;
@@ -105,3 +114,5 @@ gs::WinView gs_make_view(gs_ctx *ctx, const WindowBufs &w, int32_t cycles, int32
 gs_status gs_ensure_segs(gs_ctx *ctx, size_t n);
 hipEvent_t gs_event(gs_ctx *ctx, size_t i);
 void gs_serve_shutdown(gs_ctx *ctx);
+Design *gs_get_design(gs_ctx *ctx, int32_t id);
+void gs_graph_cache_clear(gs_ctx *ctx);

@@ -98,6 +98,8 @@ struct StimView {
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int *p, uint64_t n, unsigned int v, hipStream_t s);
 hipError_t launch_add_u64(unsigned long long *dst, const unsigned long long *src, uint64_t n, hipStream_t s);
+hipError_t launch_add_u64_guarded(unsigned long long *dst, const unsigned long long *src, uint64_t n,
+                                  const unsigned int *flags, hipStream_t s);
 
 hipError_t launch_level_init(int32_t *level, int32_t n_inputs, int32_t n_gates, hipStream_t s);
 hipError_t launch_level_step(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t *level,
@@ -105,7 +107,7 @@ hipError_t launch_level_step(const int64_t *fanin_ptr, const int32_t *fanin_net,
 hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n_gates,
                                unsigned int *cursor, int32_t *perm, int count_only, hipStream_t s);
 
-hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, uint32_t salt, hipStream_t s);
+hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0, uint32_t salt, hipStream_t s);
 
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires,
                             int32_t cap, int32_t wpb, int32_t kmax, uint32_t tpw, hipStream_t s);

@@ -124,6 +124,15 @@ __global__ void fill_u32_kernel(unsigned int *p, uint64_t n, unsigned int v)
         p[i] = v;
 }
 
+// dst += src unless a window flag (arena full / chunk overflow) is set.
+__global__ void add_u64_guarded_kernel(unsigned long long *dst, const unsigned long long *src, uint64_t n,
+                                       const unsigned int *flags)
+{
+    if (flags[0] | flags[1]) return;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] += src[i];
+}
+
 __global__ void add_u64_kernel(unsigned long long *dst, const unsigned long long *src, uint64_t n)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -149,6 +158,14 @@ hipError_t launch_fill_u32(unsigned int *p, uint64_t n, unsigned int v, hipStrea
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_u64_guarded(unsigned long long *dst, const unsigned long long *src, uint64_t n,
+                                  const unsigned int *flags, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(add_u64_guarded_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n, flags);
     return hipGetLastError();
 }
 
@@ -245,9 +262,10 @@ __device__ __forceinline__ int64_t lower_bound64(const int64_t *__restrict__ a, 
     return lo;
 }
 
-__global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, SaifAcc acc, int32_t cycle0,
+__global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0_p,
                                                      uint32_t salt, uint64_t n_waves)
 {
+    const int32_t cycle0 = *glob(cycle0_p);
     const int lane = threadIdx.x & (kLanes - 1);
     const uint32_t wib = uniform(threadIdx.x / kLanes);
     const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + wib;
@@ -293,7 +311,7 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     }
 }
 
-hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, int32_t cycle0, uint32_t salt, hipStream_t s)
+hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0, uint32_t salt, hipStream_t s)
 {
     uint64_t n_waves = (uint64_t)st.n_inputs * (uint64_t)win.n_tiles;
     if (n_waves == 0) return hipSuccess;

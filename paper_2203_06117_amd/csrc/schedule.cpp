@@ -1,0 +1,532 @@
+// Level schedule: rounds of (design, stimulus, window) pieces evaluated
+// level by level (GATSPI Section 3: a level starts once the previous level is
+// complete), as direct launches or as one captured HIP graph per round shape;
+// the plain simulate call, the batched call and the autotuner are built on it.
+#include "host.h"
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace gs;
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) return gs_fail(ctx, GS_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+struct Piece {
+    Design *d;
+    Stim *s;
+    int32_t di, si;          // ids
+    int32_t c0, cycles;
+    uint64_t chunk_base;
+    int32_t tiles;
+};
+
+struct Tuning {
+    int32_t cap, wpb, tpw;
+};
+
+struct RoundResult {
+    bool retry = false;
+    double gate_eval_ms = 0, expand_ms = 0, round_ms = 0;
+    int64_t launches = 0;
+};
+
+Tuning current_tuning(const gs_ctx *ctx)
+{
+    return Tuning{ctx->opt.lds_cap, ctx->opt.waves_per_block, ctx->opt.tiles_per_wave};
+}
+
+uint64_t chunks_of(const Piece &p)
+{
+    return (uint64_t)p.d->N * (uint64_t)p.tiles;
+}
+
+// Builds the segment tables of every level step of a round: step l holds one
+// segment per piece whose design has at least l levels.
+void build_steps(gs_ctx *ctx, const std::vector<Piece> &pieces, const std::vector<WinView> &views, const Tuning &tu,
+                 std::vector<Seg> &segs, std::vector<size_t> &step_off, std::vector<size_t> &step_n,
+                 std::vector<uint64_t> &step_waves, std::vector<int32_t> &step_kmax, std::vector<int32_t> &step_wires)
+{
+    (void)ctx;
+    int32_t maxL = 0;
+    for (const Piece &p : pieces) maxL = std::max(maxL, p.d->L);
+    uint64_t salt = 0;
+    for (const Piece &p : pieces) salt += ((uint64_t)p.d->I * p.tiles + 3) / 4;
+    for (int32_t l = 1; l <= maxL; l++) {
+        step_off.push_back(segs.size());
+        uint64_t waves = 0;
+        int32_t kmax = 1, wires = 0;
+        for (size_t i = 0; i < pieces.size(); i++) {
+            const Piece &p = pieces[i];
+            if (p.d->L < l) continue;
+            const uint32_t n_gates = p.d->level_ptr[l + 1] - p.d->level_ptr[l];
+            if (n_gates == 0) continue;
+            const uint64_t ngroup = ((uint64_t)p.tiles + tu.tpw - 1) / tu.tpw;
+            Seg g;
+            std::memset(&g, 0, sizeof(g));
+            g.wave_begin = waves;
+            g.gates = p.d->d_gates;
+            g.pins = p.d->d_pins;
+            g.gate_begin = p.d->level_ptr[l];
+            g.n_gates = n_gates;
+            g.salt = (uint32_t)salt;
+            g.win = views[i];
+            g.saif = SaifAcc{p.d->d_stage, p.d->d_stage + p.d->N, p.d->d_stage + 2 * (size_t)p.d->N};
+            const uint64_t nw = (uint64_t)n_gates * ngroup;
+            waves += nw;
+            salt += (nw + tu.wpb - 1) / tu.wpb * tu.tpw;
+            kmax = std::max(kmax, p.d->level_kmax[l]);
+            wires |= p.d->has_wires ? 1 : 0;
+            segs.push_back(g);
+        }
+        step_n.push_back(segs.size() - step_off.back());
+        step_waves.push_back(waves);
+        step_kmax.push_back(kmax);
+        step_wires.push_back(wires);
+    }
+}
+
+// Records the device work of one round on stream hs: clear flags and stripe
+// counters, clear the SAIF staging of every design in the round, expand the
+// stimulus of every piece, one gate-evaluation launch per level step, and
+// (when commit) add the staging into the designs' SAIF accumulators unless a
+// flag is set.  With timing, events bracket every launch (direct mode only).
+gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pieces, const std::vector<WinView> &views,
+                       const std::vector<Design *> &designs, const Seg *d_segs, const std::vector<size_t> &step_off,
+                       const std::vector<size_t> &step_n, const std::vector<uint64_t> &step_waves,
+                       const std::vector<int32_t> &step_kmax, const std::vector<int32_t> &step_wires, const Tuning &tu,
+                       bool commit, bool timing)
+{
+    size_t ev = 0;
+    HIPCHK(launch_fill_u64(ctx->d_misc, 4, 0ull, hs));
+    HIPCHK(launch_fill_u64(ctx->d_bump, (uint64_t)kMaxStripes * kBumpStride, 0ull, hs));
+    for (Design *d : designs) HIPCHK(launch_fill_u64(d->d_stage, 3 * (uint64_t)d->N, 0ull, hs));
+    if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
+    for (size_t i = 0; i < pieces.size(); i++) {
+        const Piece &p = pieces[i];
+        StimView sv{p.s->d_init, p.s->d_tp, p.s->d_ts, p.d->I, p.s->period};
+        SaifAcc stage{p.d->d_stage, p.d->d_stage + p.d->N, p.d->d_stage + 2 * (size_t)p.d->N};
+        HIPCHK(launch_expand(sv, views[i], stage, ctx->d_c0 + i, (uint32_t)(i * 977), hs));
+    }
+    if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
+    for (size_t k = 0; k < step_off.size(); k++) {
+        if (step_waves[k] == 0) continue;
+        if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
+        HIPCHK(launch_gate_eval(d_segs + step_off[k], (int32_t)step_n[k], step_waves[k], step_wires[k], tu.cap, tu.wpb,
+                                step_kmax[k], (uint32_t)tu.tpw, hs));
+        if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
+    }
+    if (commit)
+        for (Design *d : designs)
+            HIPCHK(launch_add_u64_guarded(d->d_saif, d->d_stage, 3 * (uint64_t)d->N, (const unsigned int *)(ctx->d_misc + 1), hs));
+    return GS_OK;
+}
+
+// Runs one round.  Window buffers must hold every piece's chunks and
+// arena_words of transitions.
+gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_words, const Tuning &tu, bool commit,
+                    bool timing, RoundResult &res)
+{
+    hipStream_t hs = ctx->stream;
+    res = RoundResult();
+    uint64_t nch = 0;
+    for (Piece &p : pieces) {
+        p.chunk_base = nch;
+        nch += chunks_of(p);
+    }
+    gs_status st = gs_window_reserve(ctx, &ctx->win, nch, arena_words);
+    if (st) return st;
+    std::vector<WinView> views;
+    for (const Piece &p : pieces) views.push_back(gs_make_view(ctx, ctx->win, p.cycles, p.s->period, p.chunk_base, chunks_of(p)));
+    std::vector<Design *> designs;
+    for (const Piece &p : pieces)
+        if (std::find(designs.begin(), designs.end(), p.d) == designs.end()) designs.push_back(p.d);
+    std::vector<Seg> segs;
+    std::vector<size_t> step_off, step_n;
+    std::vector<uint64_t> step_waves;
+    std::vector<int32_t> step_kmax, step_wires;
+    build_steps(ctx, pieces, views, tu, segs, step_off, step_n, step_waves, step_kmax, step_wires);
+    // per-piece first cycle lives in device memory so that a captured graph
+    // can be replayed for another window of the same shape
+    if (ctx->c0_cap < pieces.size()) {
+        gs_dev_free(ctx->d_c0);
+        ctx->d_c0 = nullptr;
+        ctx->c0_cap = 0;
+        if (hipMalloc((void **)&ctx->d_c0, sizeof(int32_t) * std::max<size_t>(pieces.size(), 64)) != hipSuccess) {
+            (void)hipGetLastError();
+            return gs_fail(ctx, GS_E_NOMEM, "cannot allocate the round parameter block");
+        }
+        ctx->c0_cap = std::max<size_t>(pieces.size(), 64);
+    }
+    std::vector<int32_t> c0s;
+    for (const Piece &p : pieces) c0s.push_back(p.c0);
+
+    const bool graph = ctx->opt.schedule == GS_SCHED_GRAPH;
+    const uint64_t t0 = gs_now_ns();
+    if (!graph) {
+        if ((st = gs_ensure_segs(ctx, std::max<size_t>(segs.size(), 1)))) return st;
+        if (!segs.empty())
+            HIPCHK(hipMemcpyAsync(ctx->d_segs, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice, hs));
+        HIPCHK(hipMemcpyAsync(ctx->d_c0, c0s.data(), sizeof(int32_t) * c0s.size(), hipMemcpyHostToDevice, hs));
+        if ((st = record_round(ctx, hs, pieces, views, designs, ctx->d_segs, step_off, step_n, step_waves, step_kmax,
+                               step_wires, tu, commit, timing)))
+            return st;
+    } else {
+        // graph key: everything the recorded launches depend on except the first cycles
+        std::string key;
+        auto add = [&key](uint64_t v) { key.append((const char *)&v, sizeof(v)); };
+        add((uint64_t)(uintptr_t)ctx->win.hdr); add((uint64_t)(uintptr_t)ctx->win.ends);
+        add((uint64_t)(uintptr_t)ctx->win.times); add(ctx->win.words); add((uint64_t)(uintptr_t)ctx->d_c0);
+        add((uint64_t)tu.cap); add((uint64_t)tu.wpb); add((uint64_t)tu.tpw); add(commit);
+        for (const Piece &p : pieces) {
+            add((uint64_t)p.di); add((uint64_t)p.si); add((uint64_t)p.cycles); add(p.d->version);
+        }
+        auto it = ctx->graphs.find(key);
+        if (it == ctx->graphs.end()) {
+            if (ctx->graphs.size() >= 32) gs_graph_cache_clear(ctx);
+            GraphEntry ge;
+            if (hipMalloc((void **)&ge.segs, sizeof(Seg) * std::max<size_t>(segs.size(), 1)) != hipSuccess) {
+                (void)hipGetLastError();
+                return gs_fail(ctx, GS_E_NOMEM, "cannot allocate a graph's segment table");
+            }
+            if (!segs.empty())
+                HIPCHK(hipMemcpyAsync(ge.segs, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice, hs));
+            HIPCHK(hipStreamSynchronize(hs));
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            gs_status rs = record_round(ctx, ctx->cap_stream, pieces, views, designs, ge.segs, step_off, step_n,
+                                        step_waves, step_kmax, step_wires, tu, commit, false);
+            hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+            if (rs) {
+                if (g) (void)hipGraphDestroy(g);
+                gs_dev_free(ge.segs);
+                return rs;
+            }
+            if (ce != hipSuccess) {
+                gs_dev_free(ge.segs);
+                return gs_fail(ctx, GS_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+            }
+            hipError_t ie = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                gs_dev_free(ge.segs);
+                return gs_fail(ctx, GS_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ie));
+            }
+            it = ctx->graphs.emplace(key, ge).first;
+        }
+        HIPCHK(hipMemcpyAsync(ctx->d_c0, c0s.data(), sizeof(int32_t) * c0s.size(), hipMemcpyHostToDevice, hs));
+        HIPCHK(hipEventRecord(gs_event(ctx, 0), hs));
+        HIPCHK(hipStreamWaitEvent(ctx->cap_stream, ctx->events[0], 0));
+        HIPCHK(hipGraphLaunch(it->second.exec, ctx->cap_stream));
+        HIPCHK(hipEventRecord(gs_event(ctx, 1), ctx->cap_stream));
+        HIPCHK(hipStreamWaitEvent(hs, ctx->events[1], 0));
+        ctx->stats.graph_launches++;
+    }
+    unsigned long long hflags[4];
+    std::vector<unsigned long long> hb((size_t)kMaxStripes * kBumpStride);
+    HIPCHK(hipMemcpyAsync(hflags, ctx->d_misc, sizeof(hflags), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipMemcpyAsync(hb.data(), ctx->d_bump, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    res.round_ms = (gs_now_ns() - t0) * 1e-6;
+    const unsigned int *f32 = (const unsigned int *)(hflags + 1);
+    if (timing && !graph) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
+        res.expand_ms += ms;
+        size_t e = 2;
+        for (size_t k = 0; k < step_off.size(); k++) {
+            if (step_waves[k] == 0) continue;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
+            res.gate_eval_ms += ms;
+            e += 2;
+            res.launches++;
+        }
+    } else {
+        for (size_t k = 0; k < step_off.size(); k++) res.launches += step_waves[k] ? 1 : 0;
+    }
+    const WinView &v0 = views.front();
+    uint64_t used = 0;
+    for (uint32_t i = 0; i <= v0.stripe_mask; i++) used += std::min<uint64_t>(hb[(size_t)i * kBumpStride], v0.slice_words);
+    ctx->stats.arena_words = (int64_t)used;
+    ctx->stats.spilled_lanes += f32[2];
+    if (f32[1]) return gs_fail(ctx, GS_E_CAPACITY, "more than %u transitions in one (net, 64-cycle tile)", kMaxChunk);
+    if (f32[0]) {
+        res.retry = true;
+        ctx->stats.window_retries++;
+        return GS_OK;
+    }
+    ctx->stats.gate_eval_ms += res.gate_eval_ms;
+    ctx->stats.expand_ms += res.expand_ms;
+    ctx->stats.gate_eval_launches += res.launches;
+    ctx->stats.windows += (int64_t)pieces.size();
+    for (const Piece &p : pieces) ctx->stats.gate_cycles += (int64_t)p.d->G * p.cycles;
+    // the last piece stays readable through gs_read_waveform
+    const Piece &lp = pieces.back();
+    ctx->last.design = lp.di;
+    ctx->last.stim = lp.si;
+    ctx->last.c0 = lp.c0;
+    ctx->last.cycles = lp.cycles;
+    ctx->last.chunk_base = lp.chunk_base;
+    ctx->last.n_nets = lp.d->N;
+    return GS_OK;
+}
+
+uint64_t piece_arena_guess(const Piece &p)
+{
+    return gs_arena_guess(p.d->N, p.cycles, p.s->tog_prefix[p.c0 + p.cycles] - p.s->tog_prefix[p.c0]);
+}
+
+// Runs `pieces` as rounds that fit the budget.  A round whose arena fills up
+// is retried with twice the arena; at the budget limit the round is split
+// and, for a single piece, its window is halved.
+gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, bool commit, bool timing,
+                     double *gate_eval_ms)
+{
+    std::reverse(pending.begin(), pending.end());      // pop from the back in submission order
+    uint64_t grown = 0;
+    size_t max_round = (size_t)-1;
+    while (!pending.empty()) {
+        // pack pieces while headers + arena guesses fit the budget
+        std::vector<Piece> round;
+        uint64_t hdr = 0, guess = 0;
+        while (!pending.empty() && round.size() < max_round) {
+            const Piece &p = pending.back();
+            const uint64_t hb = gs_header_bytes(p.d->N, p.cycles);
+            const uint64_t gw = piece_arena_guess(p);
+            if (!round.empty() && hdr + hb + (guess + gw) * sizeof(int32_t) > ctx->budget) break;
+            round.push_back(p);
+            pending.pop_back();
+            hdr += hb;
+            guess += gw;
+        }
+        if (hdr >= ctx->budget) {
+            Piece p = round.front();
+            if (round.size() == 1 && p.cycles > kLanes) {      // halve the window
+                Piece a = p, b = p;
+                a.cycles = p.cycles / 2;
+                a.tiles = (a.cycles + kLanes - 1) / kLanes;
+                b.c0 = p.c0 + a.cycles;
+                b.cycles = p.cycles - a.cycles;
+                b.tiles = (b.cycles + kLanes - 1) / kLanes;
+                pending.push_back(b);
+                pending.push_back(a);
+                continue;
+            }
+            return gs_fail(ctx, GS_E_NOMEM, "budget cannot hold the chunk headers of one window");
+        }
+        const uint64_t max_words = (ctx->budget - hdr) / sizeof(int32_t);
+        uint64_t words = std::min(max_words, std::max(guess, std::max(grown, ctx->win.words)));
+        RoundResult rr;
+        gs_status st = run_round(ctx, round, words, tu, commit, timing, rr);
+        if (st) return st;
+        if (gate_eval_ms) *gate_eval_ms += rr.gate_eval_ms;
+        if (!rr.retry) continue;
+        // arena full: grow, else split the round, else halve the single window
+        if (words < max_words) {
+            grown = std::min(max_words, words * 2);
+            for (auto it = round.rbegin(); it != round.rend(); ++it) pending.push_back(*it);
+        } else if (round.size() > 1) {
+            // fewer pieces per round: each round gets the whole arena
+            max_round = round.size() / 2;
+            for (auto it = round.rbegin(); it != round.rend(); ++it) pending.push_back(*it);
+        } else if (round[0].cycles > kLanes) {
+            Piece p = round[0], a = p, b = p;
+            a.cycles = p.cycles / 2;
+            a.tiles = (a.cycles + kLanes - 1) / kLanes;
+            b.c0 = p.c0 + a.cycles;
+            b.cycles = p.cycles - a.cycles;
+            b.tiles = (b.cycles + kLanes - 1) / kLanes;
+            pending.push_back(b);
+            pending.push_back(a);
+        } else {
+            return gs_fail(ctx, GS_E_NOMEM, "transitions of one 64-cycle window exceed the memory budget");
+        }
+    }
+    return GS_OK;
+}
+
+Piece make_piece(gs_ctx *ctx, int32_t di, int32_t si, int32_t c0, int32_t cycles)
+{
+    Piece p;
+    p.d = ctx->designs[di];
+    p.s = ctx->stims[si];
+    p.di = di;
+    p.si = si;
+    p.c0 = c0;
+    p.cycles = cycles;
+    p.chunk_base = 0;
+    p.tiles = (cycles + kLanes - 1) / kLanes;
+    return p;
+}
+
+int32_t default_window(gs_ctx *ctx, const Design *d)
+{
+    int32_t W = ctx->opt.window_cycles;
+    if (W <= 0) {
+        W = 4096;
+        while (W > kLanes && gs_header_bytes(d->N, W) * 3 > ctx->budget) W /= 2;
+    }
+    return W;
+}
+
+gs_status check_job(gs_ctx *ctx, int32_t design, int32_t stim, int32_t b, int32_t e)
+{
+    Design *d = gs_get_design(ctx, design);
+    if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
+    if (stim < 0 || stim >= (int32_t)ctx->stims.size() || !ctx->stims[stim] || ctx->stims[stim]->design != design)
+        return gs_fail(ctx, GS_E_INVALID, "stimulus %d does not belong to design %d", stim, design);
+    return gs_check_ranges(ctx, d, ctx->stims[stim], b, e);
+}
+
+}  // namespace
+
+void gs_graph_cache_clear(gs_ctx *ctx)
+{
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        gs_dev_free(kv.second.segs);
+    }
+    ctx->graphs.clear();
+}
+
+extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end)
+{
+    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
+    if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
+    gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
+    if (st) return st;
+    (void)hipSetDevice(ctx->opt.device);
+    const uint64_t t_start = gs_now_ns();
+    ctx->last = LastWindow();
+    Design *d = ctx->designs[design];
+    const int32_t W = default_window(ctx, d);
+    std::vector<Piece> pieces;
+    for (int32_t c0 = cycle_begin; c0 < cycle_end; c0 += W)
+        pieces.push_back(make_piece(ctx, design, stim, c0, std::min(W, cycle_end - c0)));
+    // one window per round: windows run one after another
+    for (const Piece &p : pieces) {
+        st = run_pieces(ctx, std::vector<Piece>{p}, current_tuning(ctx), true, ctx->opt.timing != 0, nullptr);
+        if (st) return st;
+    }
+    ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
+    return GS_OK;
+}
+
+// Times each candidate tuning on a trial window (nothing committed) and
+// keeps the fastest in the context.
+static gs_status autotune_impl(gs_ctx *ctx, const std::vector<Piece> &trial, Tuning *best_out, double *best_ms)
+{
+    static const Tuning cands[] = {{8, 4, 4}, {8, 4, 2}, {8, 4, 8}, {8, 2, 4}, {16, 4, 4}, {8, 8, 4}, {16, 2, 8}, {8, 4, 1}};
+    double best = 1e30;
+    Tuning bt = current_tuning(ctx);
+    const int saved_sched = ctx->opt.schedule;
+    ctx->opt.schedule = GS_SCHED_LEVELS;              // events bracket every launch
+    gs_stats saved = ctx->stats;
+    for (const Tuning &t : cands) {
+        double ms = 0;
+        gs_status st = run_pieces(ctx, trial, t, false, true, &ms);   // warm
+        if (st) { ctx->opt.schedule = saved_sched; ctx->stats = saved; return st; }
+        ms = 0;
+        st = run_pieces(ctx, trial, t, false, true, &ms);
+        if (st) { ctx->opt.schedule = saved_sched; ctx->stats = saved; return st; }
+        if (ms < best) {
+            best = ms;
+            bt = t;
+        }
+    }
+    ctx->opt.schedule = saved_sched;
+    ctx->stats = saved;
+    ctx->opt.lds_cap = bt.cap;
+    ctx->opt.waves_per_block = bt.wpb;
+    ctx->opt.tiles_per_wave = bt.tpw;
+    if (best_out) *best_out = bt;
+    if (best_ms) *best_ms = best;
+    return GS_OK;
+}
+
+extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end,
+                                 gs_tuning *out)
+{
+    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
+    if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving");
+    gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
+    if (st) return st;
+    if (cycle_end <= cycle_begin) return gs_fail(ctx, GS_E_INVALID, "empty trial range");
+    (void)hipSetDevice(ctx->opt.device);
+    std::vector<Piece> trial{make_piece(ctx, design, stim, cycle_begin, std::min(cycle_end - cycle_begin, 4096))};
+    Tuning t;
+    double ms;
+    st = autotune_impl(ctx, trial, &t, &ms);
+    if (st) return st;
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        out->lds_cap = t.cap;
+        out->waves_per_block = t.wpb;
+        out->tiles_per_wave = t.tpw;
+        out->trial_ms = ms;
+    }
+    return GS_OK;
+}
+
+extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job *jobs)
+{
+    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
+    if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return gs_fail(ctx, GS_E_INVALID, "bad job array");
+    for (int32_t i = 0; i < n_jobs; i++) {
+        gs_status st = check_job(ctx, jobs[i].design, jobs[i].stim, jobs[i].cycle_begin, jobs[i].cycle_end);
+        if (st) return st;
+    }
+    (void)hipSetDevice(ctx->opt.device);
+    const uint64_t t_start = gs_now_ns();
+    ctx->last = LastWindow();
+    std::vector<Piece> pieces;
+    int64_t best_work = -1;
+    Piece trial;
+    for (int32_t i = 0; i < n_jobs; i++) {
+        const gs_job &j = jobs[i];
+        Design *d = ctx->designs[j.design];
+        const int32_t W = default_window(ctx, d);
+        for (int32_t c0 = j.cycle_begin; c0 < j.cycle_end; c0 += W) {
+            pieces.push_back(make_piece(ctx, j.design, j.stim, c0, std::min(W, j.cycle_end - c0)));
+            const int64_t work = (int64_t)d->G * pieces.back().cycles;
+            if (work > best_work) {
+                best_work = work;
+                trial = pieces.back();
+            }
+        }
+    }
+    if (pieces.empty()) return GS_OK;
+    if (ctx->opt.autotune) {
+        // tune once per batch shape on (up to 256 cycles of) its largest piece
+        std::string key;
+        for (const Piece &p : pieces) {
+            key += std::to_string(p.di) + ":" + std::to_string(p.cycles) + ",";
+        }
+        auto it = ctx->tuned.find(key);
+        if (it == ctx->tuned.end()) {
+            trial.cycles = std::min(trial.cycles, 256);
+            trial.tiles = (trial.cycles + kLanes - 1) / kLanes;
+            Tuning t;
+            double ms;
+            gs_status st = autotune_impl(ctx, std::vector<Piece>{trial}, &t, &ms);
+            if (st) return st;
+            ctx->tuned[key] = {t.cap, t.wpb, t.tpw};
+        } else {
+            ctx->opt.lds_cap = it->second[0];
+            ctx->opt.waves_per_block = it->second[1];
+            ctx->opt.tiles_per_wave = it->second[2];
+        }
+    }
+    gs_status st = run_pieces(ctx, pieces, current_tuning(ctx), true, ctx->opt.timing != 0, nullptr);
+    if (st) return st;
+    ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
+    return GS_OK;
+}

@@ -1,10 +1,6 @@
 // Batching and serving entry points (filled in once the plain path is validated).
 #include "host.h"
 
-extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t, const gs_job *)
-{
-    return gs_fail(ctx, GS_E_STATE, "batching not available in this build");
-}
 extern "C" gs_status gs_serve_start(gs_ctx *ctx, int32_t, const int32_t *, const int32_t *, const int32_t *,
                                     const int32_t *, int32_t)
 {

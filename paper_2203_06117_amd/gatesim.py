@@ -33,7 +33,8 @@ class Options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("hbm_budget", C.c_uint64),
                 ("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("window_cycles", C.c_int32),
                 ("lds_cap", C.c_int32), ("waves_per_block", C.c_int32), ("schedule", C.c_int32),
-                ("timing", C.c_int32), ("tiles_per_wave", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("timing", C.c_int32), ("tiles_per_wave", C.c_int32), ("autotune", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class DesignInfo(C.Structure):
@@ -46,7 +47,12 @@ class Stats(C.Structure):
     _fields_ = [("gate_eval_ms", C.c_double), ("expand_ms", C.c_double), ("wall_ms", C.c_double),
                 ("gate_eval_launches", C.c_int64), ("windows", C.c_int64), ("window_retries", C.c_int64),
                 ("gate_cycles", C.c_int64), ("spilled_lanes", C.c_int64), ("arena_words", C.c_int64),
-                ("reserved", C.c_int64 * 6)]
+                ("graph_launches", C.c_int64), ("reserved", C.c_int64 * 5)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("lds_cap", C.c_int32), ("waves_per_block", C.c_int32), ("tiles_per_wave", C.c_int32),
+                ("reserved", C.c_int32), ("trial_ms", C.c_double)]
 
 
 class Job(C.Structure):
@@ -91,6 +97,7 @@ _SIGS = {
     "gs_check_arcs": (I32, [I32, P, I32, P, C.c_int64, P]),
     "gs_check_stimulus": (I32, [I32, I32, I32, P, P, P]),
     "gs_simulate_batch": (I32, [P, I32, C.POINTER(Job)]),
+    "gs_autotune": (I32, [P, I32, I32, I32, I32, C.POINTER(Tuning)]),
     "gs_serve_start": (I32, [P, I32, P, P, P, P, I32]),
     "gs_submit": (I32, [P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "gs_poll": (I32, [P, C.c_uint64, I32, C.POINTER(Result)]),
@@ -163,7 +170,8 @@ class GateSim:
 
     def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0, arena=None,
                  window_cycles: int = 0, lds_cap: int = 0, waves_per_block: int = 4,
-                 schedule: int = SCHED_LEVELS, timing: bool = False, tiles_per_wave: int = 0):
+                 schedule: int = SCHED_LEVELS, timing: bool = False, tiles_per_wave: int = 0,
+                 autotune: bool = False):
         o = Options()
         _lib.gs_default_options(C.byref(o))
         o.device = device
@@ -179,6 +187,7 @@ class GateSim:
         o.schedule = schedule
         o.timing = 1 if timing else 0
         o.tiles_per_wave = tiles_per_wave
+        o.autotune = 1 if autotune else 0
         h = P()
         st = _lib.gs_create(C.byref(o), C.byref(h))
         if st != GS_OK:
@@ -283,6 +292,12 @@ class GateSim:
         s = Stats()
         self._chk(_lib.gs_get_stats(self._h, C.byref(s), 1 if reset else 0))
         return {k: getattr(s, k) for k, _ in Stats._fields_ if k != "reserved"}
+
+    def autotune(self, design, stim, cycle_begin, cycle_end) -> dict:
+        t = Tuning()
+        self._chk(_lib.gs_autotune(self._h, design, stim, int(cycle_begin), int(cycle_end), C.byref(t)))
+        return {"lds_cap": t.lds_cap, "waves_per_block": t.waves_per_block, "tiles_per_wave": t.tiles_per_wave,
+                "trial_ms": t.trial_ms}
 
     def simulate_batch(self, jobs):
         arr = (Job * len(jobs))(*[Job(*j) for j in jobs])
