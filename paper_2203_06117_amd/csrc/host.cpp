@@ -93,13 +93,15 @@ extern "C" gs_status gs_check_netlist(int32_t n_cells, const uint8_t *n_pins, in
 static gs_status compile_arcs(gs_ctx *ctx, const std::vector<uint8_t> &gate_k, const std::vector<int64_t> &fanin_ptr,
                               int64_t n_arcs, const gs_arc *arcs, std::vector<int32_t> &q, std::vector<int32_t> &r0,
                               std::vector<int32_t> &f0, std::vector<int32_t> &r1, std::vector<int32_t> &f1,
-                              int32_t *max_delay, int32_t *zero_delay)
+                              int32_t *max_delay, int32_t *zero_delay, std::vector<int64_t> *rec_out = nullptr)
 {
     const int32_t G = (int32_t)gate_k.size();
     const int64_t F = G ? fanin_ptr[G] : 0;
     if (n_arcs < 0 || (n_arcs > 0 && !arcs)) return gs_fail(ctx, GS_E_INVALID, "bad arc array");
     // per slot: [0] unconditional record index, [1] cond val 0, [2] cond val 1
-    std::vector<int64_t> rec(3 * (size_t)F, -1);
+    std::vector<int64_t> local;
+    std::vector<int64_t> &rec = rec_out ? *rec_out : local;
+    rec.assign(3 * (size_t)F, -1);
     q.assign(F, -1);
     int64_t n_zero = 0, n_pos = 0;
     int32_t mx = 0;
@@ -503,11 +505,14 @@ extern "C" gs_status gs_load_arcs(gs_ctx *ctx, int32_t design, int64_t n_arcs, c
     Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     std::vector<int32_t> q, r0, f0, r1, f1;
+    std::vector<int64_t> rec;
     int32_t mx, zd;
-    gs_status st = compile_arcs(ctx, d->gate_k, d->fanin_ptr, n_arcs, arcs, q, r0, f0, r1, f1, &mx, &zd);
+    gs_status st = compile_arcs(ctx, d->gate_k, d->fanin_ptr, n_arcs, arcs, q, r0, f0, r1, f1, &mx, &zd, &rec);
     if (st) return st;
     if (zd && d->has_wires) return gs_fail(ctx, GS_E_INVALID, "zero-delay arcs need zero wire delays");
     d->q.swap(q); d->r0.swap(r0); d->f0.swap(f0); d->r1.swap(r1); d->f1.swap(f1);
+    d->slot_rec.swap(rec);
+    d->arcs.assign(arcs, arcs + n_arcs);
     d->max_delay = mx;
     d->zero_delay = zd;
     d->arcs_loaded = true;

@@ -29,6 +29,8 @@ struct Design {
     int32_t level_sweeps = 0;
     // compiled delays per fanin slot
     std::vector<int32_t> q, r0, f0, r1, f1, wr, wf;
+    std::vector<int64_t> slot_rec;       // per fanin slot: arc record of [uncond, cond=0, cond=1], -1 if none
+    std::vector<gs_arc> arcs;            // the loaded arc records
     bool arcs_loaded = false, has_wires = false;
     int32_t zero_delay = 0, max_delay = 0, max_wire = 0;
     uint64_t version = 0;

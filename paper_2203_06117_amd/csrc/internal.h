@@ -51,10 +51,17 @@ struct WinView {
     unsigned long long *bump;      // one counter per stripe, kBumpStride apart: words handed out in the stripe
     unsigned int *flags;           // [0] arena full, [1] chunk over 65535, [2] spilled lanes
     uint64_t slice_words;          // arena words owned by each stripe
+    uint64_t arena_off;            // first word of this window's arena, counted from `times`
     int32_t n_tiles;
     int32_t n_cycles;              // cycles in this window
     int32_t period;
     uint32_t stripe_mask;          // stripes - 1 (a power of two)
+    // Cone re-simulation: when `slot` is set, net n's chunks live at slot[n]
+    // of hdr/ends if slot[n] >= 0 (a re-simulated net) and otherwise at n of
+    // rd_hdr/rd_ends (the resident window the cone is evaluated against).
+    const int32_t *slot;
+    const ChunkHdr *rd_hdr;
+    const uint16_t *rd_ends;
 };
 
 // The transition arena is split into stripes, each with its own bump
@@ -110,6 +117,13 @@ hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n
 hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0, uint32_t salt, hipStream_t s);
 
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires,
-                            int32_t cap, int32_t wpb, int32_t kmax, uint32_t tpw, hipStream_t s);
+                            int32_t cap, int32_t wpb, int32_t kmax, uint32_t tpw, int32_t remap, hipStream_t s);
+
+// Fanout-cone marking for delay edits, one launch per level: mark[out] |= the
+// OR of mark over the gate's fanin nets (marks of edited gates preset).
+hipError_t launch_cone_mark(const GateRec *gates, const PinRec *pins, uint32_t gate_begin, uint32_t n_gates,
+                            uint8_t *mark, hipStream_t s);
+// Zeroes the SAIF counters of the output nets of gates[0 .. n).
+hipError_t launch_saif_zero(const GateRec *gates, uint32_t n, SaifAcc acc, hipStream_t s);
 
 }  // namespace gs

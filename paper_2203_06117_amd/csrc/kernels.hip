@@ -95,7 +95,7 @@ __device__ __forceinline__ bool place_chunk(const WinView &win, uint64_t ci, uin
             if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok = false;
         }
-        b += (uint64_t)stripe * win.slice_words;
+        b += win.arena_off + (uint64_t)stripe * win.slice_words;
     }
     *glob(win.ends + ci * kLanes + lane) = ok ? (uint16_t)incl : (uint16_t)0;
     if (lane == 0) {
@@ -495,7 +495,7 @@ __device__ __forceinline__ void walk(Pins<K, WIRES> &P, uint64_t truth, int32_t 
 // cycle of a tile).  The per-gate work (arc data, delay table) is done once;
 // SAIF counts of the output net are summed over the tiles and added with one
 // atomic per counter.
-template <int K, bool WIRES, int CAP>
+template <int K, bool WIRES, int CAP, bool REMAP>
 __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint32_t tile0, uint32_t ntl, int lane,
                                           uint32_t lut_base, uint32_t out_base)
 {
@@ -503,11 +503,22 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;
     Pins<K, WIRES> P;
-    int32_t net[K];
+    // chunk row of every fanin and of the output: the net id, or its slot
+    // in the re-simulated cone (REMAP; then rd_* marks a resident chunk)
+    uint32_t row[K];
+    bool resident[K];
+    uint32_t out_row = g.out;
+    if (REMAP) out_row = (uint32_t)*glob(win.slot + g.out);
 #pragma unroll
     for (int j = 0; j < K; j++) {
         const PinRec pr = *glob(sg.pins + g.pin0 + j);
-        net[j] = pr.net;
+        row[j] = (uint32_t)pr.net;
+        resident[j] = false;
+        if (REMAP) {
+            const int32_t sl = *glob(win.slot + pr.net);
+            resident[j] = sl < 0;
+            row[j] = sl < 0 ? (uint32_t)pr.net : (uint32_t)sl;
+        }
         P.q[j] = pr.q; P.r0[j] = pr.r0; P.f0[j] = pr.f0; P.r1[j] = pr.r1; P.f1[j] = pr.f1;
         P.wr[j] = pr.wr; P.wf[j] = pr.wf;
     }
@@ -528,13 +539,19 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         uint32_t state0 = 0;
 #pragma unroll
         for (int j = 0; j < K; j++) {
-            const uint64_t ci = (uint64_t)(uint32_t)net[j] * ntile + tile;
+            const uint64_t ci = (uint64_t)row[j] * ntile + tile;
+            const ChunkHdr *hsrc = win.hdr;
+            const uint16_t *esrc = win.ends;
+            if (REMAP && resident[j]) {
+                hsrc = win.rd_hdr;
+                esrc = win.rd_ends;
+            }
             // the chunk header is wave-uniform: one load, moved to scalar registers
-            const ChunkHdr hv = *glob(win.hdr + ci);
+            const ChunkHdr hv = *glob(hsrc + ci);
             ChunkHdr h;
             h.off = uniform64(hv.off);
             h.mask = uniform64(hv.mask);
-            const uint32_t e = *glob(win.ends + ci * kLanes + lane);
+            const uint32_t e = *glob(esrc + ci * kLanes + lane);
             const uint32_t lo = wave_shr1(e);
             P.chunk[j] = win.times + h.off;
             P.idx[j] = idx0[j] = active ? lo : 0u;
@@ -550,7 +567,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         const uint32_t incl = wave_incl_scan(ucnt);
         const uint32_t total = (uint32_t)lane63(incl);
         const uint64_t mask = __ballot(active && y0);
-        const uint64_t ci = (uint64_t)g.out * ntile + tile;
+        const uint64_t ci = (uint64_t)out_row * ntile + tile;
         uint64_t base;
         const bool ok = place_chunk(win, ci, incl, total, mask, lane, sg.salt + tt, base);
         if (ok) {
@@ -599,7 +616,7 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int n, uin
 
 // Wave w of a launch -> (segment, gate, group of tpw consecutive tiles).
 // LDS per wave: 64 words of delay table, then CAP x 64 staged output words.
-template <bool WIRES, int CAP, int KMAX>
+template <bool WIRES, int CAP, int KMAX, bool REMAP>
 __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ segs, int32_t n_segs, uint64_t n_waves,
                                                         uint32_t tpw)
 {
@@ -621,17 +638,17 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const uint32_t lut_base = wib * (kLanes + CAP * kLanes);
     const uint32_t out_base = lut_base + kLanes;
     switch (g.k) {
-    case 1: eval_gate<1, WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 2: eval_gate<2, WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 3: eval_gate<3, WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 1: eval_gate<1, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 2: eval_gate<2, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 3: eval_gate<3, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
     default: break;
     }
 }
 
-template <bool WIRES, int KMAX>
+template <bool WIRES, int KMAX, bool REMAP>
 static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t cap, int32_t wpb, uint32_t tpw,
                             hipStream_t s)
 {
@@ -639,25 +656,75 @@ static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
     const size_t lds = (size_t)wpb * ((size_t)cap * kLanes + kLanes) * sizeof(int32_t);
     const dim3 grid((unsigned)blocks), block(kLanes * wpb);
     switch (cap) {
-    case 4: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 4, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
-    case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
-    case 16: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 16, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
-    case 32: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 32, KMAX>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 16: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 16, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 32: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 32, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 4: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 4, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <bool REMAP>
+static hipError_t launch_ge_r(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires, int32_t cap,
+                              int32_t wpb, int32_t kmax, uint32_t tpw, hipStream_t s)
+{
+    if (kmax <= 3)
+        return wires ? launch_ge<true, 3, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s)
+                     : launch_ge<false, 3, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s);
+    return wires ? launch_ge<true, 6, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s)
+                 : launch_ge<false, 6, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s);
+}
+
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires, int32_t cap,
-                            int32_t wpb, int32_t kmax, uint32_t tpw, hipStream_t s)
+                            int32_t wpb, int32_t kmax, uint32_t tpw, int32_t remap, hipStream_t s)
 {
     if (n_waves == 0) return hipSuccess;
     if (wpb < 1 || wpb > 8 || tpw < 1) return hipErrorInvalidValue;
-    if (kmax <= 3)
-        return wires ? launch_ge<true, 3>(segs, n_segs, n_waves, cap, wpb, tpw, s)
-                     : launch_ge<false, 3>(segs, n_segs, n_waves, cap, wpb, tpw, s);
-    return wires ? launch_ge<true, 6>(segs, n_segs, n_waves, cap, wpb, tpw, s)
-                 : launch_ge<false, 6>(segs, n_segs, n_waves, cap, wpb, tpw, s);
+    return remap ? launch_ge_r<true>(segs, n_segs, n_waves, wires, cap, wpb, kmax, tpw, s)
+                 : launch_ge_r<false>(segs, n_segs, n_waves, wires, cap, wpb, kmax, tpw, s);
+}
+
+// --------------------------------------------------------------------------
+// Delay-edit support: fanout-cone marking (one launch per level, in level
+// order, so a gate sees the final marks of every fanin) and clearing of the
+// re-simulated nets' SAIF counters.
+// --------------------------------------------------------------------------
+__global__ void cone_mark_kernel(const GateRec *__restrict__ gates, const PinRec *__restrict__ pins, uint32_t gate_begin,
+                                 uint32_t n_gates, uint8_t *mark)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_gates) return;
+    const GateRec g = gates[gate_begin + i];
+    uint8_t m = mark[g.out];
+    for (uint32_t j = 0; j < g.k; j++) m |= mark[pins[g.pin0 + j].net];
+    mark[g.out] = m;
+}
+
+hipError_t launch_cone_mark(const GateRec *gates, const PinRec *pins, uint32_t gate_begin, uint32_t n_gates,
+                            uint8_t *mark, hipStream_t s)
+{
+    if (n_gates == 0) return hipSuccess;
+    hipLaunchKernelGGL(cone_mark_kernel, dim3((n_gates + 255) / 256), dim3(256), 0, s, gates, pins, gate_begin, n_gates,
+                       mark);
+    return hipGetLastError();
+}
+
+__global__ void saif_zero_kernel(const GateRec *__restrict__ gates, uint32_t n, SaifAcc acc)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t o = gates[i].out;
+    acc.tc[o] = 0;
+    acc.t0[o] = 0;
+    acc.t1[o] = 0;
+}
+
+hipError_t launch_saif_zero(const GateRec *gates, uint32_t n, SaifAcc acc, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(saif_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, gates, n, acc);
+    return hipGetLastError();
 }
 
 }  // namespace gs

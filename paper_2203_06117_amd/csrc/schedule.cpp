@@ -120,7 +120,7 @@ gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pi
         if (step_waves[k] == 0) continue;
         if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
         HIPCHK(launch_gate_eval(d_segs + step_off[k], (int32_t)step_n[k], step_waves[k], step_wires[k], tu.cap, tu.wpb,
-                                step_kmax[k], (uint32_t)tu.tpw, hs));
+                                step_kmax[k], (uint32_t)tu.tpw, 0, hs));
         if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     }
     if (commit)
