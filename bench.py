@@ -11,6 +11,13 @@ Also reported (one JSON line):
                 launch time (HIP events on the library's stream) vs 8 TB/s
   cpu_baseline  the CPU oracle timed on a bounded prefix of the same workload
                 (single thread), whose SAIF also re-checks the GPU result
+  batched       64 uneven instances (1e4-5e5 gates, 200-5000 cycles) run as
+                one batch (autotuned, replayed from a captured HIP graph):
+                aggregate gate-cycles/s beside the same jobs run one by one,
+                with every instance's SAIF compared between the two
+  served        9 resident netlists, Poisson-arriving window and delay-edit
+                requests (200/s for 60 s): req/s, p50/p99 latency, served
+                gate-cycles/s, and a sample re-run alone and compared
 """
 import argparse
 import json
@@ -44,62 +51,36 @@ def algorithmic_bytes(net, tc, n_cycles, n_tiles):
     return list_reads + list_writes + headers + meta
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cycles", type=int, default=10_000)
-    ap.add_argument("--window", type=int, default=1000)
-    ap.add_argument("--lds-cap", type=int, default=8)
-    ap.add_argument("--tpw", type=int, default=4)
-    ap.add_argument("--wpb", type=int, default=4)
-    ap.add_argument("--cpu-cycles", type=int, default=30, help="oracle sample: first N cycles (0 = skip)")
-    ap.add_argument("--no-timing", action="store_true")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="run one plain device copy of this many MiB first (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU cycle sharding is a design "
-                                   "note only (see DESIGN.md)", "n_gpus": args.gpus}))
-        sys.exit(2)
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
-    import torch
-    from paper_2203_06117_amd import synth
-    from paper_2203_06117_amd.gatesim import GateSim
 
+def run_scale(args, torch, synth, GateSim):
     t_gen = time.time()
     w = synth.scale(n_cycles=args.cycles)
-    gen_s = time.time() - t_gen
     net, stim = w["netlist"], w["stimulus"]
     Gn, C = net["n_gates"], stim["n_cycles"]
-    print(f"[bench] workload {w['name']}: {Gn} gates, {net['n_inputs']} inputs, {C} cycles, "
-          f"{int(stim['toggle_ptr'][-1])} input toggles (generated in {gen_s:.1f}s)", file=sys.stderr, flush=True)
-
-    torch.cuda.init()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    log(f"workload {w['name']}: {Gn} gates, {net['n_inputs']} inputs, {C} cycles, "
+        f"{int(stim['toggle_ptr'][-1])} input toggles (generated in {time.time() - t_gen:.1f}s)")
     stream = torch.cuda.current_stream()
     sim = GateSim(device=0, stream=stream, window_cycles=args.window, lds_cap=args.lds_cap,
                   waves_per_block=args.wpb, timing=not args.no_timing, tiles_per_wave=args.tpw)
     t_load = time.time()
     d, s = sim.load_work(w)
-    load_s = time.time() - t_load
     info = sim.design_info(d)
-    print(f"[bench] loaded in {load_s:.1f}s, {info.n_levels} levels", file=sys.stderr, flush=True)
-
+    log(f"loaded in {time.time() - t_load:.1f}s, {info.n_levels} levels")
     if args.calib_copy_mib:
         n = args.calib_copy_mib << 18
-        a = torch.ones(n, dtype=torch.int32, device=dev)
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
         torch.add(a, 1, out=b)          # one elementwise kernel: reads n*4 bytes, writes n*4 bytes
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr, flush=True)
+        log(f"calibration kernel: {n * 4} bytes read, {n * 4} bytes written")
         del a, b
     for i in range(args.warmup):
         sim.simulate(d, s, 0, C)
         sim.read_saif(d, reset=True)
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        log(f"warmup {i + 1}/{args.warmup} done")
     sim.stats(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -112,24 +93,21 @@ def main():
     st = sim.stats()
     elapsed = t1 - t0
     gate_cycles = Gn * C * args.steps
-    value = gate_cycles / elapsed
-    print(f"[bench] {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
-
+    log(f"{args.steps} steps in {elapsed:.3f}s")
     tc = saif[0]
     n_tiles_total = sum((min(args.window, C - c0) + 63) // 64 for c0 in range(0, C, args.window))
     alg_bytes_step = algorithmic_bytes(net, tc, C, n_tiles_total)
     launches = st["gate_eval_launches"]
     roofline = None
     if not args.no_timing and launches:
-        ge_s = st["gate_eval_ms"] / 1e3
-        avg_launch_s = ge_s / launches
+        avg_launch_s = st["gate_eval_ms"] / 1e3 / launches
         per_launch_bytes = alg_bytes_step * args.steps / launches
         achieved = per_launch_bytes / avg_launch_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "kernel": "gate_eval_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                    "launches": launches, "bytes_per_gate_cycle": round(alg_bytes_step / (Gn * C), 3)}
-
+                    "launches": launches, "bytes_per_launch": round(per_launch_bytes),
+                    "bytes_per_gate_cycle": round(alg_bytes_step / (Gn * C), 3)}
     cpu = None
     if args.cpu_cycles > 0:
         import oracle
@@ -145,22 +123,12 @@ def main():
         cpu = {"value": round(Gn * nc / cpu_s, 1), "unit": "gate-cycles/s", "cores": 1, "kind": "oracle",
                "sample": f"cycles 0..{nc} of the 1M-gate workload ({Gn * nc:.3g} gate-cycles, {cpu_s:.1f} s)",
                "gpu_parity_on_sample": parity}
-        print(f"[bench] oracle sample {nc} cycles in {cpu_s:.1f}s, parity {parity}", file=sys.stderr, flush=True)
-
+        log(f"oracle sample {nc} cycles in {cpu_s:.1f}s, parity {parity}")
+    sim.close()
     a_bar = float(tc[net["n_inputs"]:].sum()) / (Gn * C)
-    out = {
-        "metric": METRIC,
-        "value": round(value, 1),
-        "unit": "gate-cycles/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    return {
+        "value": round(gate_cycles / elapsed, 1),
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
         "config": {"workload": "scale-1M", "gates": Gn, "inputs": net["n_inputs"], "levels": info.n_levels,
                    "cycles": C, "period_ps": stim["period"], "toggle_p": 0.15, "delays_ps": "5-80",
                    "cond_frac": 0.10, "window_cycles": args.window, "lds_cap": args.lds_cap,
@@ -172,7 +140,207 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+
+
+def run_batch(args, torch, synth, G):
+    t_gen = time.time()
+    works = synth.batched()
+    gc = [w["netlist"]["n_gates"] * w["stimulus"]["n_cycles"] for w in works]
+    log(f"batched: {len(works)} instances, {sum(w['netlist']['n_gates'] for w in works)} gates, "
+        f"{sum(gc):.3g} gate-cycles (generated in {time.time() - t_gen:.1f}s)")
+    sim = G.GateSim(device=0, stream=torch.cuda.current_stream(), schedule=G.SCHED_GRAPH, autotune=True)
+    ids = [sim.load_work(w, cells_loaded=i > 0) for i, w in enumerate(works)]
+    jobs = [(d, s, 0, w["stimulus"]["n_cycles"]) for (d, s), w in zip(ids, works)]
+    t_w = time.perf_counter()
+    sim.simulate_batch(jobs)                                   # autotune + capture
+    for d, _ in ids:
+        sim.read_saif(d, reset=True)
+    log(f"batched warmup (autotune + capture) {time.perf_counter() - t_w:.1f}s")
+    steps = max(1, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.simulate_batch(jobs)
+        batch_saif = [sim.read_saif(d, reset=True) for d, _ in ids]
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    st = sim.stats()
+    # the same jobs one by one (plain path, default tuning, per-level launches)
+    plain = G.GateSim(device=0, stream=torch.cuda.current_stream())
+    pids = [plain.load_work(w, cells_loaded=i > 0) for i, w in enumerate(works)]
+    for (d, s), w in zip(pids, works):                          # warm
+        plain.simulate(d, s, 0, min(64, w["stimulus"]["n_cycles"]))
+        plain.read_saif(d, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alone = []
+    for (d, s), w in zip(pids, works):
+        plain.simulate(d, s, 0, w["stimulus"]["n_cycles"])
+        alone.append(plain.read_saif(d, reset=True))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = all(all(np.array_equal(a, b) for a, b in zip(x, y)) for x, y in zip(batch_saif, alone))
+    # oracle sample: the first 6 cycles of the three smallest instances, as a batch
+    import oracle
+    small = sorted(range(len(works)), key=lambda i: works[i]["netlist"]["n_gates"])[:3]
+    sim.simulate_batch([(ids[i][0], ids[i][1], 0, 6) for i in small])
+    ok_oracle = True
+    for i in small:
+        ref = oracle.simulate(works[i], 0, 6)
+        got = sim.read_saif(ids[i][0], reset=True)
+        ok_oracle &= all(np.array_equal(a, ref[k]) for a, k in zip(got, ("tc", "t0", "t1")))
     sim.close()
+    plain.close()
+    log(f"batched {t_batch * 1e3:.1f} ms/step vs one-by-one {t_plain * 1e3:.1f} ms; alone==batch {same}, "
+        f"oracle sample {ok_oracle}")
+    return {"workload": "batched-64", "instances": len(works), "gate_cycles": int(sum(gc)),
+            "value": round(sum(gc) / t_batch, 1), "unit": "gate-cycles/s", "ms_per_step": round(t_batch * 1e3, 3),
+            "one_by_one_gate_cycles_per_s": round(sum(gc) / t_plain, 1),
+            "speedup_vs_one_by_one": round(t_plain / t_batch, 3),
+            "graph_launches": st["graph_launches"], "schedule": "captured HIP graph, autotuned",
+            "bit_exact_batch_vs_alone": bool(same), "oracle_sample_ok": bool(ok_oracle)}
+
+
+def run_serve(args, torch, synth, G):
+    import threading
+    t_gen = time.time()
+    works = synth.served_designs()
+    log(f"served: {len(works)} resident netlists, {sum(w['netlist']['n_gates'] for w in works)} gates "
+        f"(generated in {time.time() - t_gen:.1f}s)")
+    sim = G.GateSim(device=0)
+    ids = [sim.load_work(w, cells_loaded=i > 0) for i, w in enumerate(works)]
+    resident = [(d, s, 0, 1000) for d, s in ids]
+    t_r = time.perf_counter()
+    sim.serve_start(resident, max_queue=1 << 20)
+    log(f"resident windows ready in {time.perf_counter() - t_r:.1f}s")
+    rng = np.random.default_rng(5)
+    rate, dur = args.serve_rate, args.serve_seconds
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * dur * 1.5)))
+    arrivals = arrivals[arrivals < dur]
+    plan = []
+    for t in arrivals:
+        i = int(rng.integers(len(works)))
+        if rng.random() < 0.5:
+            n = int(rng.integers(100, 2001))
+            C = works[i]["stimulus"]["n_cycles"]
+            b = int(rng.integers(0, C - n + 1))
+            plan.append((t, "w", i, (b, b + n)))
+        else:
+            a = works[i]["arcs"]
+            k = int(rng.integers(1, 501))
+            idx = rng.choice(len(a["gate"]), size=k, replace=False)
+            ed = [(int(a["gate"][j]), int(a["pin"][j]), int(a["cond_pin"][j]), int(a["cond_val"][j]),
+                   max(1, int(round(a["rise"][j] * (1 + rng.uniform(-0.2, 0.2))))),
+                   max(1, int(round(a["fall"][j] * (1 + rng.uniform(-0.2, 0.2)))))) for j in idx]
+            plan.append((t, "e", i, ed))
+    sample = set(int(x) for x in rng.choice(len(plan), size=min(40, len(plan)), replace=False))
+    tickets = [None] * len(plan)
+    kept = {}
+    lat, gcs, done_t, sub_t, status = [], [], [], [], []
+    lock = threading.Lock()
+
+    def submit(p):
+        _, kind, i, arg = p
+        return sim.submit_window(*ids[i], *arg) if kind == "w" else sim.submit_edit(*ids[i], arg)
+
+    def producer():
+        t0 = time.perf_counter()
+        for j, p in enumerate(plan):
+            wait = p[0] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            tk = submit(p)
+            with lock:
+                tickets[j] = tk
+
+    def consumer():
+        for j in range(len(plan)):
+            while True:
+                with lock:
+                    tk = tickets[j]
+                if tk is not None:
+                    break
+                time.sleep(0.0005)
+            r = sim.poll(tk, wait=True)
+            sim.release(tk)
+            status.append(r["status"])
+            lat.append((r["t_done_ns"] - r["t_submit_ns"]) * 1e-6)
+            gcs.append(r["gate_cycles"])
+            done_t.append(r["t_done_ns"])
+            sub_t.append(r["t_submit_ns"])
+            if j in sample and r["status"] == 0:
+                kept[j] = (r["tc"], r["t0"], r["t1"])
+            if (j + 1) % 2000 == 0:
+                log(f"served {j + 1}/{len(plan)} requests")
+
+    th = [threading.Thread(target=producer), threading.Thread(target=consumer)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    wall = (max(done_t) - min(sub_t)) * 1e-9
+    # a sample of requests again, one at a time, compared with the mixed run
+    same = True
+    for j in sorted(kept):
+        tk = submit(plan[j])
+        r = sim.poll(tk, wait=True)
+        sim.release(tk)
+        same &= r["status"] == 0 and all(np.array_equal(a, b) for a, b in zip((r["tc"], r["t0"], r["t1"]), kept[j]))
+    sim.serve_stop()
+    sim.close()
+    lat = np.array(lat)
+    ok = int(sum(1 for x in status if x == 0))
+    log(f"served {ok}/{len(plan)} ok, {ok / wall:.1f} req/s, p50 {np.percentile(lat, 50):.1f} ms, "
+        f"p99 {np.percentile(lat, 99):.1f} ms, alone==mix on {len(kept)} sampled: {same}")
+    return {"workload": "served-9", "offered_req_per_s": rate, "seconds": dur, "requests": len(plan),
+            "completed_ok": ok, "value": round(ok / wall, 2), "unit": "req/s",
+            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "served_gate_cycles_per_s": round(float(sum(gcs)) / wall, 1),
+            "alone_equals_mix_sampled": bool(same), "sampled": len(kept)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", choices=["all", "scale", "batch", "serve"], default="all")
+    ap.add_argument("--cycles", type=int, default=10_000)
+    ap.add_argument("--window", type=int, default=1000)
+    ap.add_argument("--lds-cap", type=int, default=8)
+    ap.add_argument("--tpw", type=int, default=4)
+    ap.add_argument("--wpb", type=int, default=4)
+    ap.add_argument("--cpu-cycles", type=int, default=30, help="oracle sample: first N cycles (0 = skip)")
+    ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one elementwise kernel over this many MiB first (counter calibration)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU cycle sharding is a design "
+                                   "note only (see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2203_06117_amd import synth
+    from paper_2203_06117_amd import gatesim as G
+
+    torch.cuda.init()
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC, "value": None, "unit": "gate-cycles/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": {}}
+    if args.mode in ("all", "scale"):
+        out.update(run_scale(args, torch, synth, G.GateSim))
+    if args.mode in ("all", "batch"):
+        out["batched"] = run_batch(args, torch, synth, G)
+    if args.mode in ("all", "serve"):
+        out["served"] = run_serve(args, torch, synth, G)
+    if out["value"] is None:
+        leg = out.get("batched") or out.get("served")
+        out["value"], out["unit"] = leg["value"], leg["unit"]
+        out["config"] = {"workload": leg["workload"]}
     print(json.dumps(out), flush=True)
 
 

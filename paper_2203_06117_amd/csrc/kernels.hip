@@ -24,6 +24,29 @@ __device__ __forceinline__ GAS T *glob(T *p)
     return (GAS T *)p;
 }
 
+// Read-only view for wave-uniform data that the current launch never
+// writes (gate and pin records, and chunk headers of lower levels, written
+// by earlier launches): uniform addresses then load through the scalar
+// cache with s_load.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CAS __attribute__((address_space(4)))
+#else
+#define CAS
+#endif
+
+template <typename T>
+__device__ __forceinline__ const CAS T *kons(const T *p)
+{
+    return (const CAS T *)p;
+}
+
+// Transitions in chunk ci (the inclusive lane end of its last lane).
+__device__ __forceinline__ uint32_t chunk_total(const uint16_t *ends, uint64_t ci)
+{
+    const uint32_t w = *kons((const uint32_t *)(ends + ci * kLanes + kLanes - 2));
+    return w >> 16;
+}
+
 
 // --------------------------------------------------------------------------
 // wave-level helpers
@@ -128,7 +151,7 @@ __global__ void fill_u32_kernel(unsigned int *p, uint64_t n, unsigned int v)
 __global__ void add_u64_guarded_kernel(unsigned long long *dst, const unsigned long long *src, uint64_t n,
                                        const unsigned int *flags)
 {
-    if (flags[0] | flags[1]) return;
+    if (flags[0] | flags[1] | flags[3]) return;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         dst[i] += src[i];
 }
@@ -508,14 +531,14 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
     uint32_t row[K];
     bool resident[K];
     uint32_t out_row = g.out;
-    if (REMAP) out_row = (uint32_t)*glob(win.slot + g.out);
+    if (REMAP) out_row = (uint32_t)*kons(win.slot + g.out);
 #pragma unroll
     for (int j = 0; j < K; j++) {
-        const PinRec pr = *glob(sg.pins + g.pin0 + j);
+        const PinRec pr = *kons(sg.pins + g.pin0 + j);
         row[j] = (uint32_t)pr.net;
         resident[j] = false;
         if (REMAP) {
-            const int32_t sl = *glob(win.slot + pr.net);
+            const int32_t sl = *kons(win.slot + pr.net);
             resident[j] = sl < 0;
             row[j] = sl < 0 ? (uint32_t)pr.net : (uint32_t)sl;
         }
@@ -528,6 +551,34 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // One arena reservation for all tiles of the wave, issued before any
+    // walk so that its latency overlaps the work: a lane's output never has
+    // more edges than its pins have events, so the fanin chunk sizes bound
+    // the output chunks (Algorithm 1 appends at most one edge per event).
+    uint32_t bound = 0;
+    for (uint32_t tt = 0; tt < ntl; tt++) {
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const uint16_t *esrc = (REMAP && resident[j]) ? win.rd_ends : win.ends;
+            bound += chunk_total(esrc, (uint64_t)row[j] * ntile + tile0 + tt);
+        }
+    }
+    uint64_t wbase = 0;
+    bool wok = true;
+    if (bound > 0) {
+        const uint32_t stripe = (blockIdx.x + sg.salt) & win.stripe_mask;
+        uint64_t b = 0;
+        if (lane == 0)
+            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)bound,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b = uniform64(b);
+        if (b + bound > win.slice_words) {
+            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            wok = false;
+        }
+        wbase = win.arena_off + (uint64_t)stripe * win.slice_words + b;
+    }
+    uint64_t used = 0;
     const uint32_t out_lane = out_base + lane;
     uint32_t tc_sum = 0, nact_sum = 0;
     int32_t t1_lane = 0;
@@ -546,11 +597,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 hsrc = win.rd_hdr;
                 esrc = win.rd_ends;
             }
-            // the chunk header is wave-uniform: one load, moved to scalar registers
-            const ChunkHdr hv = *glob(hsrc + ci);
-            ChunkHdr h;
-            h.off = uniform64(hv.off);
-            h.mask = uniform64(hv.mask);
+            const ChunkHdr h = *kons(hsrc + ci);
             const uint32_t e = *glob(esrc + ci * kLanes + lane);
             const uint32_t lo = wave_shr1(e);
             P.chunk[j] = win.times + h.off;
@@ -568,8 +615,24 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         const uint32_t total = (uint32_t)lane63(incl);
         const uint64_t mask = __ballot(active && y0);
         const uint64_t ci = (uint64_t)out_row * ntile + tile;
-        uint64_t base;
-        const bool ok = place_chunk(win, ci, incl, total, mask, lane, sg.salt + tt, base);
+        bool ok = wok;
+        if (total > kMaxChunk) {
+            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+        }
+        if (used + total > bound) {                    // cannot happen (bound above); never write past it
+            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+        }
+        const uint64_t base = wbase + used;
+        if (ok) used += total;
+        *glob(win.ends + ci * kLanes + lane) = ok ? (uint16_t)incl : (uint16_t)0;
+        if (lane == 0) {
+            ChunkHdr h;
+            h.off = ok ? base : 0;
+            h.mask = mask;
+            *glob(win.hdr + ci) = h;
+        }
         if (ok) {
             int32_t *out = win.times + base + (incl - ucnt);
             const int32_t n = cnt < CAP ? cnt : CAP;
@@ -634,7 +697,7 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const uint32_t grp = local - gi * ngroup;
     const uint32_t tile0 = grp * tpw;
     const uint32_t ntl = min(tpw, ntile - tile0);
-    const GateRec g = *glob(sg.gates + sg.gate_begin + gi);
+    const GateRec g = *kons(sg.gates + sg.gate_begin + gi);
     const uint32_t lut_base = wib * (kLanes + CAP * kLanes);
     const uint32_t out_base = lut_base + kLanes;
     switch (g.k) {

@@ -596,6 +596,8 @@ void serve_loop(gs_ctx *ctx, ServeState *S)
             const unsigned long long *hb = (const unsigned long long *)(h + 3 * 8 * N + 16);
             if (e != hipSuccess) {
                 finish(S, *q, GS_E_DEVICE, hipGetErrorString(e));
+            } else if (fl[3]) {
+                finish(S, *q, GS_E_DEVICE, "internal error: an output chunk exceeded its fanin bound");
             } else if (fl[1]) {
                 finish(S, *q, GS_E_CAPACITY, "more than 65535 transitions in one (net, 64-cycle tile)");
             } else if (fl[0]) {
@@ -747,6 +749,7 @@ extern "C" gs_status gs_serve_start(gs_ctx *ctx, int32_t n_resident, const int32
             unsigned int fl[4];
             if (hipMemcpyAsync(fl, q.flags, sizeof(fl), hipMemcpyDeviceToHost, S->st) != hipSuccess ||
                 hipStreamSynchronize(S->st) != hipSuccess) { st = GS_E_DEVICE; err = "resident window"; break; }
+            if (fl[3]) { st = GS_E_DEVICE; err = "internal error: an output chunk exceeded its fanin bound"; break; }
             if (fl[1]) { st = GS_E_CAPACITY; err = "resident window exceeds 65535 transitions per chunk"; break; }
             if (!fl[0]) break;
             S->pool.release(q.region);

@@ -359,3 +359,40 @@ def small_random(seed: int, n_gates: int, n_inputs: int, n_levels: int, n_cycles
             "arcs": make_arcs(seed, net, dlo, dhi, cond_frac), "wires": wires,
             "stimulus": make_stimulus(seed, n_inputs, n_cycles, period, p, skew=skew,
                                       extra=extra, extra_p=extra_p)}
+
+
+def batched(seed: int = 4, n: int = 64) -> list:
+    """Uneven independent instances: gates log-uniform in [1e4, 5e5],
+    inputs = gates / 50, levels 24 + 96 ln(G/1e4) / ln 50, cycles
+    log-uniform in [200, 5000], toggle p uniform in [0.05, 0.3], delays
+    5-80 ps with 10% COND cells, 800 ps cycles; instance i uses seed 400 + i."""
+    s = Stream(seed, "batch-shapes")
+    i = np.arange(n, dtype=np.int64)
+    G = np.exp(np.log(1e4) + s.unit(4 * i) * (np.log(5e5) - np.log(1e4))).astype(np.int64)
+    C = np.exp(np.log(200) + s.unit(4 * i + 1) * (np.log(5000) - np.log(200))).astype(np.int64)
+    P = 0.05 + 0.25 * s.unit(4 * i + 2)
+    out = []
+    for k in range(n):
+        g = int(G[k])
+        L = int(round(24 + 96 * np.log(g / 1e4) / np.log(50)))
+        net = make_netlist(400 + k, g, max(3, g // 50), L)
+        out.append({"name": f"batch-{k}", "netlist": net, "arcs": make_arcs(400 + k, net, 5, 80, 0.10),
+                    "wires": None,
+                    "stimulus": make_stimulus(400 + k, max(3, g // 50), int(C[k]), 800, float(P[k]), skew=50)})
+    return out
+
+
+def served_designs(seed: int = 5, scale_cycles: int = 4000, small_cycles: int = 2500) -> list:
+    """The 1M-gate design plus eight designs of 5e4-2e5 gates (log-uniform,
+    seeds 501..508) with delays 5-80 ps and 10% COND cells, 800 ps cycles,
+    toggle probability 0.15."""
+    s = Stream(seed, "served-shapes")
+    out = [scale(2, n_cycles=scale_cycles)]
+    for k in range(8):
+        g = int(np.exp(np.log(5e4) + float(s.unit(np.array([k]))[0]) * (np.log(2e5) - np.log(5e4))))
+        L = int(round(24 + 96 * np.log(g / 1e4) / np.log(50)))
+        net = make_netlist(501 + k, g, max(3, g // 50), L)
+        out.append({"name": f"served-{k}", "netlist": net, "arcs": make_arcs(501 + k, net, 5, 80, 0.10),
+                    "wires": None,
+                    "stimulus": make_stimulus(501 + k, max(3, g // 50), small_cycles, 800, 0.15, skew=50)})
+    return out
