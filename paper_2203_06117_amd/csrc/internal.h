@@ -119,10 +119,24 @@ hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *c
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires,
                             int32_t cap, int32_t wpb, int32_t kmax, uint32_t tpw, int32_t remap, hipStream_t s);
 
+// New delays of one edited fanin slot, addressed by (output net, pin).
+struct EditRec {
+    uint32_t out;
+    uint32_t pin;
+    int32_t r0, f0, r1, f1;
+};
+
 // Fanout-cone marking for delay edits, one launch per level: mark[out] |= the
-// OR of mark over the gate's fanin nets (marks of edited gates preset).
+// OR of mark over the gate's fanin nets (marks of edited gates preset);
+// *count counts the level's marked gates.
 hipError_t launch_cone_mark(const GateRec *gates, const PinRec *pins, uint32_t gate_begin, uint32_t n_gates,
-                            uint8_t *mark, hipStream_t s);
+                            uint8_t *mark, unsigned int *count, hipStream_t s);
+hipError_t launch_mark_set(const uint32_t *nets, uint32_t n, uint8_t *mark, hipStream_t s);
+hipError_t launch_cone_place(const GateRec *gates, const PinRec *pins, uint32_t n_gates, const uint8_t *mark,
+                             const int32_t *level, const unsigned int *off, unsigned int *cur, GateRec *cg, PinRec *cp,
+                             uint32_t stride, int32_t *slot, uint32_t n_cone, hipStream_t s);
+hipError_t launch_edit_apply(const EditRec *ed, uint32_t n, const int32_t *slot, PinRec *cp, uint32_t stride,
+                             uint32_t n_cone, hipStream_t s);
 // Zeroes the SAIF counters of the output nets of gates[0 .. n).
 hipError_t launch_saif_zero(const GateRec *gates, uint32_t n, SaifAcc acc, hipStream_t s);
 

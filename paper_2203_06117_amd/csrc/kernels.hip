@@ -754,7 +754,7 @@ hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
 // re-simulated nets' SAIF counters.
 // --------------------------------------------------------------------------
 __global__ void cone_mark_kernel(const GateRec *__restrict__ gates, const PinRec *__restrict__ pins, uint32_t gate_begin,
-                                 uint32_t n_gates, uint8_t *mark)
+                                 uint32_t n_gates, uint8_t *mark, unsigned int *count)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_gates) return;
@@ -762,14 +762,85 @@ __global__ void cone_mark_kernel(const GateRec *__restrict__ gates, const PinRec
     uint8_t m = mark[g.out];
     for (uint32_t j = 0; j < g.k; j++) m |= mark[pins[g.pin0 + j].net];
     mark[g.out] = m;
+    if (m) atomicAdd(count, 1u);
 }
 
 hipError_t launch_cone_mark(const GateRec *gates, const PinRec *pins, uint32_t gate_begin, uint32_t n_gates,
-                            uint8_t *mark, hipStream_t s)
+                            uint8_t *mark, unsigned int *count, hipStream_t s)
 {
     if (n_gates == 0) return hipSuccess;
     hipLaunchKernelGGL(cone_mark_kernel, dim3((n_gates + 255) / 256), dim3(256), 0, s, gates, pins, gate_begin, n_gates,
-                       mark);
+                       mark, count);
+    return hipGetLastError();
+}
+
+__global__ void mark_set_kernel(const uint32_t *__restrict__ nets, uint32_t n, uint8_t *mark)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) mark[nets[i]] = 1;
+}
+
+hipError_t launch_mark_set(const uint32_t *nets, uint32_t n, uint8_t *mark, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(mark_set_kernel, dim3((n + 255) / 256), dim3(256), 0, s, nets, n, mark);
+    return hipGetLastError();
+}
+
+// Copies the marked gates (and their pins, at a fixed stride) into a
+// level-ordered cone: level l occupies [off[l], off[l+1]); the order inside
+// a level follows arrival at the level's cursor (evaluation order inside a
+// level does not matter).  slot[out] receives the gate's cone position.
+__global__ void cone_place_kernel(const GateRec *__restrict__ gates, const PinRec *__restrict__ pins, uint32_t n_gates,
+                                  const uint8_t *__restrict__ mark, const int32_t *__restrict__ level,
+                                  const unsigned int *__restrict__ off, unsigned int *cur, GateRec *cg, PinRec *cp,
+                                  uint32_t stride, int32_t *slot, uint32_t n_cone)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_gates) return;
+    GateRec g = gates[p];
+    if (!mark[g.out]) return;
+    const int32_t l = level[g.out];
+    const uint32_t pos = off[l] + atomicAdd(&cur[l], 1u);
+    if (pos >= off[l + 1] || pos >= n_cone) return;      // counts and marks disagree: never write outside the cone
+    const uint32_t pin0 = g.pin0;
+    g.pin0 = pos * stride;
+    cg[pos] = g;
+    for (uint32_t j = 0; j < g.k; j++) cp[pos * stride + j] = pins[pin0 + j];
+    slot[g.out] = (int32_t)pos;
+}
+
+hipError_t launch_cone_place(const GateRec *gates, const PinRec *pins, uint32_t n_gates, const uint8_t *mark,
+                             const int32_t *level, const unsigned int *off, unsigned int *cur, GateRec *cg, PinRec *cp,
+                             uint32_t stride, int32_t *slot, uint32_t n_cone, hipStream_t s)
+{
+    if (n_gates == 0) return hipSuccess;
+    hipLaunchKernelGGL(cone_place_kernel, dim3((n_gates + 255) / 256), dim3(256), 0, s, gates, pins, n_gates, mark, level,
+                       off, cur, cg, cp, stride, slot, n_cone);
+    return hipGetLastError();
+}
+
+// Writes edited arc delays into the cone's pin records.
+__global__ void edit_apply_kernel(const EditRec *__restrict__ ed, uint32_t n, const int32_t *__restrict__ slot,
+                                  PinRec *cp, uint32_t stride, uint32_t n_cone)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const EditRec e = ed[i];
+    const int32_t sl = slot[e.out];
+    if (sl < 0 || (uint32_t)sl >= n_cone || e.pin >= stride) return;
+    PinRec &r = cp[(uint32_t)sl * stride + e.pin];
+    r.r0 = e.r0;
+    r.f0 = e.f0;
+    r.r1 = e.r1;
+    r.f1 = e.f1;
+}
+
+hipError_t launch_edit_apply(const EditRec *ed, uint32_t n, const int32_t *slot, PinRec *cp, uint32_t stride,
+                             uint32_t n_cone, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(edit_apply_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ed, n, slot, cp, stride, n_cone);
     return hipGetLastError();
 }
 

@@ -118,6 +118,16 @@ struct Req {
     uint32_t n_cone = 0;
     int pinned = -1;
     hipEvent_t ev = nullptr;
+    // delay edits: cone preparation scratch (marks, per-level counts and
+    // offsets, net -> cone slot, edited records)
+    Region prep;
+    uint8_t *d_mark = nullptr;
+    unsigned int *d_cnt = nullptr, *d_cur = nullptr, *d_off = nullptr;
+    int32_t *d_slot = nullptr;
+    EditRec *d_edits = nullptr;
+    uint32_t *d_enets = nullptr;
+    uint32_t stride = 1;
+    hipEvent_t ev_prep = nullptr;
 };
 
 using ReqP = std::shared_ptr<Req>;
@@ -145,6 +155,8 @@ struct ServeState {
     void *pinned[kPinned] = {};
     uint64_t pinned_bytes = 0;
     bool pinned_busy[kPinned] = {};
+    Seg *h_seg_ring = nullptr;                          // pinned staging of the segment tables
+    char *h_small = nullptr;                            // pinned staging of edit records and level offsets
     std::map<Design *, double> words_per_net_cycle;   // observed arena need
     uint64_t salt = 0;
     gs_status fatal = GS_OK;
@@ -187,7 +199,6 @@ uint64_t region_bytes(uint64_t rows, int32_t tiles, uint64_t words, uint64_t n_n
     b += align256((uint64_t)kMaxStripes * kBumpStride * sizeof(unsigned long long));
     b += 256;                                               // flags + first cycle
     if (edit) {
-        b += align256(n_nets * sizeof(int32_t));
         b += align256(cone_gates * sizeof(GateRec));
         b += align256(cone_pins * sizeof(PinRec));
     }
@@ -227,11 +238,9 @@ void layout(ServeState *S, Req &q, uint64_t rows)
     q.view.period = q.s->period;
     q.acc = SaifAcc{saif, saif + q.d->N, saif + 2 * (size_t)q.d->N};
     if (q.r.kind == GS_REQ_EDIT) {
-        int32_t *slot = at<int32_t>(S, o);
-        o += align256((uint64_t)q.d->N * sizeof(int32_t));
         GateRec *g = at<GateRec>(S, o);
         o += align256((uint64_t)q.n_cone * sizeof(GateRec));
-        q.view.slot = slot;
+        q.view.slot = q.d_slot;
         q.view.rd_hdr = S->res[q.res_idx].hdr;
         q.view.rd_ends = S->res[q.res_idx].ends;
         q.gates = g;
@@ -263,6 +272,7 @@ gs_status start_request(gs_ctx *ctx, ServeState *S, Req &q, std::string &err)
         SCHK(launch_expand(sv, q.view, q.acc, q.d_c0, (uint32_t)(S->salt++ * 131), hs));
     } else {
         const Resident &R = S->res[q.res_idx];
+        SCHK(hipStreamWaitEvent(hs, q.ev_prep, 0));
         SCHK(hipMemcpyAsync(q.acc.tc, R.saif, 3 * sizeof(unsigned long long) * q.d->N, hipMemcpyDeviceToDevice, hs));
         SCHK(launch_saif_zero(q.gates, q.n_cone, q.acc, hs));
     }
@@ -302,20 +312,22 @@ gs_status admit(gs_ctx *ctx, ServeState *S, Req &q, bool &fits, std::string &err
         q.gate_cycles = (int64_t)d->G * q.cycles;
         return GS_OK;
     }
-    // delay edit: new delays per touched fanin slot
+    // delay edit: new delays per touched fanin slot, computed from the
+    // slot's arc records with the edited records substituted
     const Resident &R = S->res[q.res_idx];
     q.c0 = R.c0;
     q.cycles = R.cycles;
     q.tiles = R.tiles;
     std::map<int64_t, std::array<int32_t, 2>> newdel;     // arc record -> (rise, fall)
+    std::map<int64_t, int32_t> slots;                     // touched fanin slot -> gate
     for (const gs_arc_edit &e : q.edits) {
         if (e.gate < 0 || e.gate >= d->G || e.pin < 0 || e.pin >= d->gate_k[e.gate]) {
             err = "edit names a pin that does not exist";
             return GS_E_INVALID;
         }
-        const int64_t s = d->fanin_ptr[e.gate] + e.pin;
+        const int64_t sl = d->fanin_ptr[e.gate] + e.pin;
         const int which = e.cond_pin < 0 ? 0 : 1 + (e.cond_val ? 1 : 0);
-        const int64_t a = d->slot_rec[3 * s + which];
+        const int64_t a = d->slot_rec[3 * sl + which];
         if (a < 0 || (e.cond_pin >= 0 && d->arcs[a].cond_pin != e.cond_pin)) {
             err = "edit names an arc record that does not exist";
             return GS_E_INVALID;
@@ -327,90 +339,118 @@ gs_status admit(gs_ctx *ctx, ServeState *S, Req &q, bool &fits, std::string &err
             return GS_E_INVALID;
         }
         newdel[a] = {e.rise_ps, e.fall_ps};
+        slots[sl] = e.gate;
     }
-    // mark the fanout cone on the device (preparation stream)
-    std::vector<uint8_t> mark(d->N, 0);
-    for (const gs_arc_edit &e : q.edits) mark[d->I + e.gate] = 1;
-    uint8_t *d_mark = nullptr;
-    Region mr;
-    if (!S->pool.alloc(align256(d->N), mr)) {
-        fits = false;
-        return GS_OK;
+    if (slots.size() > 65536) {
+        err = "at most 65536 edited pins per request";
+        return GS_E_INVALID;
     }
-    d_mark = at<uint8_t>(S, mr.off);
-    hipError_t he = hipMemcpyAsync(d_mark, mark.data(), d->N, hipMemcpyHostToDevice, S->prep);
+    std::vector<EditRec> er;
+    std::vector<uint32_t> enets;
+    for (auto &kv : slots) {
+        const int64_t sl = kv.first;
+        const int32_t g = kv.second;
+        const int64_t u = d->slot_rec[3 * sl], a0 = d->slot_rec[3 * sl + 1] >= 0 ? d->slot_rec[3 * sl + 1] : u,
+                      a1 = d->slot_rec[3 * sl + 2] >= 0 ? d->slot_rec[3 * sl + 2] : u;
+        auto del = [&](int64_t a, int rise) -> int32_t {
+            auto it = newdel.find(a);
+            if (it != newdel.end()) return it->second[rise ? 0 : 1];
+            return rise ? d->arcs[a].rise_ps : d->arcs[a].fall_ps;
+        };
+        EditRec e;
+        e.out = (uint32_t)(d->I + g);
+        e.pin = (uint32_t)(sl - d->fanin_ptr[g]);
+        e.r0 = del(a0, 1); e.f0 = del(a0, 0); e.r1 = del(a1, 1); e.f1 = del(a1, 0);
+        er.push_back(e);
+        if (enets.empty() || enets.back() != e.out) enets.push_back(e.out);
+    }
+    // preparation scratch: marks, counts, cursors, offsets, slots, edit records
+    const uint64_t L2 = (uint64_t)d->L + 2;
+    uint64_t pb = 0;
+    const uint64_t o_mark = pb;  pb += align256(d->N);
+    const uint64_t o_cnt = pb;   pb += align256(L2 * 4);
+    const uint64_t o_cur = pb;   pb += align256(L2 * 4);
+    const uint64_t o_off = pb;   pb += align256(L2 * 4);
+    const uint64_t o_slot = pb;  pb += align256((uint64_t)d->N * 4);
+    const uint64_t o_ed = pb;    pb += align256(er.size() * sizeof(EditRec));
+    const uint64_t o_en = pb;    pb += align256(enets.size() * 4);
+    if (!q.prep.bytes) {
+        if (!S->pool.alloc(pb, q.prep)) {
+            fits = false;
+            return GS_OK;
+        }
+    }
+    q.d_mark = at<uint8_t>(S, q.prep.off + o_mark);
+    q.d_cnt = at<unsigned int>(S, q.prep.off + o_cnt);
+    q.d_cur = at<unsigned int>(S, q.prep.off + o_cur);
+    q.d_off = at<unsigned int>(S, q.prep.off + o_off);
+    q.d_slot = at<int32_t>(S, q.prep.off + o_slot);
+    q.d_edits = at<EditRec>(S, q.prep.off + o_ed);
+    q.d_enets = at<uint32_t>(S, q.prep.off + o_en);
+    // mark the fanout cone level by level on the preparation stream and
+    // read back the per-level cone sizes (the only host wait of an edit)
+    hipStream_t ps = S->prep;
+    char *h_ed = S->h_small, *h_off = S->h_small + (2u << 20);
+    std::memcpy(h_ed, er.data(), er.size() * sizeof(EditRec));
+    std::memcpy(h_ed + (1u << 20) + (512u << 10), enets.data(), enets.size() * 4);
+    hipError_t he = launch_fill_u32((unsigned int *)q.d_mark, (d->N + 3) / 4, 0u, ps);
+    if (he == hipSuccess) he = launch_fill_u32(q.d_cnt, L2, 0u, ps);
+    if (he == hipSuccess) he = launch_fill_u32(q.d_cur, L2, 0u, ps);
+    if (he == hipSuccess) he = launch_fill_u32((unsigned int *)q.d_slot, d->N, 0xffffffffu, ps);
+    if (he == hipSuccess) he = hipMemcpyAsync(q.d_edits, h_ed, er.size() * sizeof(EditRec), hipMemcpyHostToDevice, ps);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(q.d_enets, h_ed + (1u << 20) + (512u << 10), enets.size() * 4, hipMemcpyHostToDevice, ps);
+    if (he == hipSuccess) he = launch_mark_set(q.d_enets, (uint32_t)enets.size(), q.d_mark, ps);
     for (int32_t l = 1; l <= d->L && he == hipSuccess; l++)
-        he = launch_cone_mark(d->d_gates, d->d_pins, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l], d_mark,
-                              S->prep);
-    if (he == hipSuccess) he = hipMemcpyAsync(mark.data(), d_mark, d->N, hipMemcpyDeviceToHost, S->prep);
-    if (he == hipSuccess) he = hipStreamSynchronize(S->prep);
-    S->pool.release(mr);
+        he = launch_cone_mark(d->d_gates, d->d_pins, d->level_ptr[l], d->level_ptr[l + 1] - d->level_ptr[l], q.d_mark,
+                              q.d_cnt + l, ps);
+    std::vector<unsigned int> cnt(L2, 0);
+    if (he == hipSuccess) he = hipMemcpyAsync(h_off, q.d_cnt, L2 * 4, hipMemcpyDeviceToHost, ps);
+    if (he == hipSuccess) he = hipStreamSynchronize(ps);
     if (he != hipSuccess) {
         err = std::string("cone marking: ") + hipGetErrorString(he);
         return GS_E_DEVICE;
     }
-    // cone gates in level order, their slots and records with the edits applied
-    std::vector<int32_t> slot(d->N, -1);
-    std::vector<GateRec> cg;
-    std::vector<PinRec> cp;
+    std::memcpy(cnt.data(), h_off, L2 * 4);
+    std::vector<unsigned int> off(L2, 0);
     q.lvl_begin.clear();
     q.lvl_n.clear();
+    uint32_t total = 0;
     for (int32_t l = 1; l <= d->L; l++) {
-        const uint32_t b = (uint32_t)cg.size();
-        for (uint32_t p = d->level_ptr[l]; p < d->level_ptr[l + 1]; p++) {
-            const int32_t g = d->perm[p];
-            if (!mark[d->I + g]) continue;
-            slot[d->I + g] = (int32_t)cg.size();
-            GateRec r;
-            std::memset(&r, 0, sizeof(r));
-            r.out = (uint32_t)(d->I + g);
-            r.pin0 = (uint32_t)cp.size();
-            r.k = d->gate_k[g];
-            r.truth = d->gate_truth[g];
-            cg.push_back(r);
-            for (int64_t s = d->fanin_ptr[g]; s < d->fanin_ptr[g + 1]; s++) {
-                PinRec pr;
-                pr.net = d->fanin_net[s];
-                pr.q = d->q[s];
-                pr.wr = d->wr[s];
-                pr.wf = d->wf[s];
-                const int64_t u = d->slot_rec[3 * s], a0 = d->slot_rec[3 * s + 1] >= 0 ? d->slot_rec[3 * s + 1] : u,
-                              a1 = d->slot_rec[3 * s + 2] >= 0 ? d->slot_rec[3 * s + 2] : u;
-                auto del = [&](int64_t a, int rise) -> int32_t {
-                    auto it = newdel.find(a);
-                    if (it != newdel.end()) return it->second[rise ? 0 : 1];
-                    return rise ? d->arcs[a].rise_ps : d->arcs[a].fall_ps;
-                };
-                pr.r0 = del(a0, 1); pr.f0 = del(a0, 0); pr.r1 = del(a1, 1); pr.f1 = del(a1, 0);
-                cp.push_back(pr);
-            }
-        }
-        q.lvl_begin.push_back(b);
-        q.lvl_n.push_back((uint32_t)cg.size() - b);
+        off[l] = total;
+        q.lvl_begin.push_back(total);
+        q.lvl_n.push_back(cnt[l]);
+        total += cnt[l];
     }
-    q.n_cone = (uint32_t)cg.size();
-    if (!q.arena_words) q.arena_words = guess_words(S, d, q.n_cone, q.cycles, 0);
+    off[d->L + 1] = total;
+    q.n_cone = total;
+    q.stride = (uint32_t)std::max(1, d->max_pins);
+    if (!q.arena_words) q.arena_words = guess_words(S, d, std::max<uint32_t>(q.n_cone, 1), q.cycles, 0);
     const uint64_t need = region_bytes(std::max<uint32_t>(q.n_cone, 1), q.tiles, q.arena_words, d->N, q.n_cone,
-                                       cp.size(), true);
+                                       (uint64_t)q.n_cone * q.stride, true);
     if (need > S->pool.bytes) {
         err = "request does not fit the serving pool";
         return GS_E_NOMEM;
     }
     if (!S->pool.alloc(need, q.region)) {
-        fits = false;
+        fits = false;                      // keeps its preparation region; marking is redone on retry
         return GS_OK;
     }
     layout(S, q, std::max<uint32_t>(q.n_cone, 1));
-    he = hipMemcpyAsync((void *)q.view.slot, slot.data(), sizeof(int32_t) * d->N, hipMemcpyHostToDevice, S->prep);
-    if (he == hipSuccess && !cg.empty())
-        he = hipMemcpyAsync((void *)q.gates, cg.data(), sizeof(GateRec) * cg.size(), hipMemcpyHostToDevice, S->prep);
-    if (he == hipSuccess && !cp.empty())
-        he = hipMemcpyAsync((void *)q.pins, cp.data(), sizeof(PinRec) * cp.size(), hipMemcpyHostToDevice, S->prep);
-    if (he == hipSuccess) he = hipStreamSynchronize(S->prep);
+    // place the cone's records and apply the edits, still on the preparation stream
+    std::memcpy(h_off, off.data(), L2 * 4);
+    he = hipMemcpyAsync(q.d_off, h_off, L2 * 4, hipMemcpyHostToDevice, ps);
+    if (he == hipSuccess)
+        he = launch_cone_place(d->d_gates, d->d_pins, (uint32_t)d->G, q.d_mark, d->d_level, q.d_off, q.d_cur,
+                               (GateRec *)q.gates, (PinRec *)q.pins, q.stride, q.d_slot, q.n_cone, ps);
+    if (he == hipSuccess)
+        he = launch_edit_apply(q.d_edits, (uint32_t)er.size(), q.d_slot, (PinRec *)q.pins, q.stride, q.n_cone, ps);
+    if (he == hipSuccess && !q.ev_prep) he = hipEventCreateWithFlags(&q.ev_prep, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventRecord(q.ev_prep, ps);
     if (he != hipSuccess) {
         S->pool.release(q.region);
         q.region = Region();
-        err = std::string("cone upload: ") + hipGetErrorString(he);
+        err = std::string("cone placement: ") + hipGetErrorString(he);
         return GS_E_DEVICE;
     }
     q.gate_cycles = (int64_t)q.n_cone * q.cycles;
@@ -471,7 +511,9 @@ gs_status launch_step(gs_ctx *ctx, ServeState *S, std::vector<ReqP> &run, std::s
             return GS_E_STATE;
         }
         Seg *dst = S->seg_ring + (size_t)slot * S->seg_cap;
-        SCHK(hipMemcpyAsync(dst, segs[kind].data(), sizeof(Seg) * segs[kind].size(), hipMemcpyHostToDevice, S->st));
+        Seg *stage = S->h_seg_ring + (size_t)slot * S->seg_cap;
+        std::memcpy(stage, segs[kind].data(), sizeof(Seg) * segs[kind].size());
+        SCHK(hipMemcpyAsync(dst, stage, sizeof(Seg) * segs[kind].size(), hipMemcpyHostToDevice, S->st));
         SCHK(launch_gate_eval(dst, (int32_t)segs[kind].size(), waves[kind], wires[kind], ctx->opt.lds_cap,
                               ctx->opt.waves_per_block, kmax[kind], tpw, kind, S->st));
         SCHK(hipEventRecord(S->ring_ev[slot], S->st));
@@ -487,6 +529,10 @@ void finish(ServeState *S, Req &q, gs_status st, const std::string &msg)
     q.state = Q_DONE;
     if (q.region.bytes) S->pool.release(q.region);
     q.region = Region();
+    if (q.prep.bytes) S->pool.release(q.prep);
+    q.prep = Region();
+    if (q.ev_prep) (void)hipEventDestroy(q.ev_prep);
+    q.ev_prep = nullptr;
     if (q.pinned >= 0) S->pinned_busy[q.pinned] = false;
     q.pinned = -1;
     if (q.ev) (void)hipEventDestroy(q.ev);
@@ -589,11 +635,22 @@ void serve_loop(gs_ctx *ctx, ServeState *S)
                 i++;
                 continue;
             }
-            std::lock_guard<std::mutex> lk(S->mu);
+            // results are copied out of the pinned buffer before taking the lock
             const char *h = (const char *)S->pinned[q->pinned];
             const size_t N = (size_t)q->d->N;
             const unsigned int *fl = (const unsigned int *)(h + 3 * 8 * N);
             const unsigned long long *hb = (const unsigned long long *)(h + 3 * 8 * N + 16);
+            const bool good = e == hipSuccess && !fl[0] && !fl[1] && !fl[3];
+            if (good) {
+                q->tc.resize(N);
+                q->t0.resize(N);
+                q->t1.resize(N);
+                const unsigned long long *a = (const unsigned long long *)h;
+                std::memcpy(q->tc.data(), a, 8 * N);
+                std::memcpy(q->t0.data(), a + N, 8 * N);
+                std::memcpy(q->t1.data(), a + 2 * N, 8 * N);
+            }
+            std::lock_guard<std::mutex> lk(S->mu);
             if (e != hipSuccess) {
                 finish(S, *q, GS_E_DEVICE, hipGetErrorString(e));
             } else if (fl[3]) {
@@ -613,15 +670,9 @@ void serve_loop(gs_ctx *ctx, ServeState *S)
                 q->state = Q_WAIT;
                 S->queue.push_front(q);
             } else {
-                q->tc.resize(N);
-                q->t0.resize(N);
-                q->t1.resize(N);
-                const unsigned long long *a = (const unsigned long long *)h;
-                std::memcpy(q->tc.data(), a, 8 * N);
-                std::memcpy(q->t0.data(), a + N, 8 * N);
-                std::memcpy(q->t1.data(), a + 2 * N, 8 * N);
                 uint64_t used = 0;
-                for (uint32_t s = 0; s <= q->view.stripe_mask; s++) used += std::min<uint64_t>(hb[(size_t)s * kBumpStride], q->view.slice_words);
+                for (uint32_t st2 = 0; st2 <= q->view.stripe_mask; st2++)
+                    used += std::min<uint64_t>(hb[(size_t)st2 * kBumpStride], q->view.slice_words);
                 const double rows = q->r.kind == GS_REQ_EDIT ? std::max<uint32_t>(q->n_cone, 1) : q->d->N;
                 const double wpc = (double)used / (rows * q->cycles);
                 double &est = S->words_per_net_cycle[q->d];
@@ -661,6 +712,8 @@ void gs_serve_shutdown(gs_ctx *ctx)
     for (int i = 0; i < kPinned; i++)
         if (S->pinned[i]) (void)hipHostFree(S->pinned[i]);
     gs_dev_free(S->seg_ring);
+    if (S->h_seg_ring) (void)hipHostFree(S->h_seg_ring);
+    if (S->h_small) (void)hipHostFree(S->h_small);
     gs_dev_free(S->pool_ptr);
     if (S->st) (void)hipStreamDestroy(S->st);
     if (S->prep) (void)hipStreamDestroy(S->prep);
@@ -717,6 +770,9 @@ extern "C" gs_status gs_serve_start(gs_ctx *ctx, int32_t n_resident, const int32
     }
     for (int i = 0; i < kRing; i++)
         if (hipEventCreateWithFlags(&S->ring_ev[i], hipEventDisableTiming) != hipSuccess) return fail(GS_E_DEVICE, "event");
+    if (hipHostMalloc((void **)&S->h_seg_ring, sizeof(Seg) * S->seg_cap * kRing, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&S->h_small, 4u << 20, hipHostMallocDefault) != hipSuccess)
+        return fail(GS_E_NOMEM, "cannot allocate pinned staging buffers");
     int32_t max_n = 1;
     for (Design *d : ctx->designs)
         if (d) max_n = std::max(max_n, d->N);

@@ -337,6 +337,8 @@ class GateSim:
         n = res.n_nets
         out = {"status": res.status, "gate_cycles": res.gate_cycles, "t_submit_ns": res.t_submit_ns,
                "t_admit_ns": res.t_admit_ns, "t_done_ns": res.t_done_ns}
+        if res.status != GS_OK:
+            out["error"] = _lib.gs_last_error(self._h).decode()
         if res.status == GS_OK:
             out["tc"] = np.ctypeslib.as_array(res.tc, shape=(n,)).copy()
             out["t0"] = np.ctypeslib.as_array(res.t0, shape=(n,)).copy()

@@ -73,7 +73,7 @@ def served(G):
 def result_of(sim, t):
     r = sim.poll(t, wait=True)
     sim.release(t)
-    assert r["status"] == 0
+    assert r["status"] == 0, r.get("error")
     return r
 
 
