@@ -51,6 +51,23 @@ def algorithmic_bytes(net, tc, n_cycles, n_tiles):
     return list_reads + list_writes + headers + meta
 
 
+def measured_traffic():
+    """HBM bytes per gate-eval launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gate_eval_scale1M_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2203_06117_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -104,7 +121,7 @@ def run_scale(args, torch, synth, GateSim):
         per_launch_bytes = alg_bytes_step * args.steps / launches
         achieved = per_launch_bytes / avg_launch_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "kernel": "gate_eval_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
                     "launches": launches, "bytes_per_launch": round(per_launch_bytes),
                     "bytes_per_gate_cycle": round(alg_bytes_step / (Gn * C), 3)}

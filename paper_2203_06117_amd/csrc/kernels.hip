@@ -300,14 +300,30 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     const bool active = lc < win.n_cycles;
     const int64_t T = st.period;
     const int64_t c0 = (int64_t)(cycle0 + lc) * T;
-    const int64_t lo = st.toggle_ptr[i], hi = st.toggle_ptr[i + 1];
+    const int64_t lo = *kons(st.toggle_ptr + i), hi = *kons(st.toggle_ptr + i + 1);
+    // the tile's toggles first (wave-uniform search), then each lane's
+    // cycle inside that short range
+    const int64_t tile_t0 = (int64_t)(cycle0 + (int32_t)(tile * kLanes)) * T;
+    int64_t ta = lo, tb = hi;
+    while (ta < tb) {
+        const int64_t mid = (ta + tb) >> 1;
+        if (*kons(st.toggle_ps + mid) < tile_t0) ta = mid + 1;
+        else tb = mid;
+    }
+    int64_t tz = ta;
+    tb = hi;
+    while (tz < tb) {
+        const int64_t mid = (tz + tb) >> 1;
+        if (*kons(st.toggle_ps + mid) < tile_t0 + kLanes * T) tz = mid + 1;
+        else tb = mid;
+    }
     int64_t s = 0, e = 0;
     if (active) {
-        s = lower_bound64(st.toggle_ps, lo, hi, c0);
-        e = lower_bound64(st.toggle_ps, s, hi, c0 + T);
+        s = lower_bound64(st.toggle_ps, ta, tz, c0);
+        e = lower_bound64(st.toggle_ps, s, tz, c0 + T);
     }
     const uint32_t cnt = (uint32_t)(e - s);
-    const int v0 = active ? (int)((st.init[i] + (uint64_t)(s - lo)) & 1) : 0;
+    const int v0 = active ? (int)((*kons(st.init + i) + (uint64_t)(s - lo)) & 1) : 0;
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t total = (uint32_t)lane63(incl);
     const uint64_t mask = __ballot(v0 != 0);

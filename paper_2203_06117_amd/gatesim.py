@@ -17,6 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libgatesim.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+# PyTorch ships its own HIP runtime, whose libraries request it under an
+# unversioned name.  Loading torch first makes this library bind to that
+# same runtime (same soname); loading it after this library would put a
+# second HIP runtime in the process, and one of them would see no device.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 GS_OK, GS_E_INVALID, GS_E_NOT_DAG, GS_E_NOMEM, GS_E_DEVICE, GS_E_STATE, GS_E_BUSY, GS_E_CAPACITY = \

@@ -227,3 +227,31 @@ def test_scale_config_sample(G):
     assert_same(w, got, ref, "scale")
     for (n, c), g_, o_ in zip(probes, waves, ref["probes"]):
         assert g_ == o_, (n, c)
+
+
+def test_glitchy_config_sample(G):
+    """The 8M-gate glitch-heavy workload (30% ripple-carry-like XOR/MUX
+    chains, 2,000 cycles) with windows sized by the planner to fit memory:
+    the SAIF difference of GPU runs over [0, 999) and [0, 1000) is cycle
+    999, compared net by net with the oracle; lanes above the on-chip
+    staging cap take the spill path."""
+    w = synth.glitchy()
+    N = 150_000 + 8_000_000
+    rng = np.random.default_rng(2)
+    probes = [(int(n), 999) for n in rng.integers(150_000, N, 200)]
+    say("glitchy: oracle")
+    ref = oracle.simulate(w, 999, 1000, probes=probes)
+    say("glitchy: gpu")
+    with G.GateSim() as sim:
+        d, s = sim.load_work(w)
+        sim.simulate(d, s, 0, 999)
+        lo = sim.read_saif(d, reset=True)
+        sim.simulate(d, s, 0, 1000)
+        hi = sim.read_saif(d, reset=True)
+        waves = [sim.read_waveform(d, s, n, c) for n, c in probes]
+        st = sim.stats()
+    got = tuple(h - l for h, l in zip(hi, lo))
+    assert_same(w, got, ref, "glitchy")
+    for (n, c), g_, o_ in zip(probes, waves, ref["probes"]):
+        assert g_ == o_, (n, c)
+    assert st["spilled_lanes"] > 0
