@@ -14,6 +14,9 @@ SOURCES = ["kernels.hip", "host.cpp", "schedule.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # the kernels' atomics are issued by one lane; the wave-aggregation
+         # rewrite would only add a wait for every returned value
+         "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

@@ -383,6 +383,9 @@ hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *c
 // --------------------------------------------------------------------------
 extern __shared__ int32_t gs_lds[];
 
+// Fanin words a wave stages in LDS for one group of tiles.
+constexpr uint32_t kStageWords = 512;
+
 // chunk[idx] with a 32-bit byte offset from a wave-uniform base, so the
 // load can use the scalar-base + vector-offset addressing mode
 __device__ __forceinline__ int32_t ld_word(const int32_t *chunk, uint32_t idx)
@@ -390,50 +393,29 @@ __device__ __forceinline__ int32_t ld_word(const int32_t *chunk, uint32_t idx)
     return *(const GAS int32_t *)((const GAS char *)glob(chunk) + (uint64_t)(idx << 2));
 }
 
-// Per-lane walk state of one gate over one cycle; the per-pin arc data are
-// wave-uniform.
-template <int K, bool WIRES>
-struct Pins {
-    const int32_t *chunk[K];
-    uint32_t idx[K], end[K];
-    int32_t a[K];
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Arc data of one gate's pins (wave-uniform).
+template <int K>
+struct Arcs {
     int32_t q[K], r0[K], f0[K], r1[K], f1[K], wr[K], wf[K];
-    uint32_t state;
 
-    __device__ __forceinline__ void advance(int j)
-    {
-        if (!WIRES) {
-            a[j] = idx[j] < end[j] ? ld_word(chunk[j], idx[j]) : kInf;
-            return;
-        }
-        const int pv = (state >> j) & 1;
-        for (;;) {
-            if (idx[j] >= end[j]) {
-                a[j] = kInf;
-                return;
-            }
-            const int32_t e0 = ld_word(chunk[j], idx[j]);
-            const int32_t d = pv ? wf[j] : wr[j];       // the net edge goes to !pv
-            if (idx[j] + 1 < end[j] && ld_word(chunk[j], idx[j] + 1) - e0 < d) {
-                idx[j] += 2;                            // pulse narrower than the wire delay
-                continue;
-            }
-            a[j] = e0 + d;
-            return;
-        }
-    }
-
-    // Smallest arc delay over the pins in sw for output value y, in the
-    // current pin state (gates with more than three pins; smaller gates
-    // read it from the wave's lookup table).
-    __device__ __forceinline__ int32_t delay(uint32_t sw, int y) const
+    // Smallest arc delay over the pins in sw for output value y, in pin
+    // state st (gates with more than three pins; smaller gates read it from
+    // the wave's lookup table).
+    __device__ __forceinline__ int32_t delay(uint32_t st, uint32_t sw, int y) const
     {
         int32_t d = kInf;
 #pragma unroll
         for (int j = 0; j < K; j++) {
             // arithmetic selects: a select between array elements would
             // become an address select and force the arrays to scratch
-            const int32_t sel = -(int32_t)((state >> q[j]) & 1);
+            const int32_t sel = -(int32_t)((st >> q[j]) & 1);
             const int32_t rise = r0[j] + (sel & (r1[j] - r0[j]));
             const int32_t fall = f0[j] + (sel & (f1[j] - f0[j]));
             const int32_t dj = fall + ((-y) & (rise - fall));
@@ -444,21 +426,70 @@ struct Pins {
     }
 };
 
+// Per-lane cursor over one gate's fanin lists in one cycle: pin j's next
+// event is word idx[j] of its chunk (a[j] = its arrival time).  LDSRC: the
+// chunk was staged in LDS by the wave and starts at word base[j] of the
+// wave's LDS; otherwise it is read from the transition arena at chunk[j].
+template <int K, bool WIRES, bool LDSRC>
+struct Cursor {
+    const int32_t *chunk[K];
+    uint32_t base[K];
+    uint32_t idx[K], end[K];
+    int32_t a[K];
+    uint32_t state;
+
+    __device__ __forceinline__ int32_t word(int j, uint32_t i) const
+    {
+        if (LDSRC) return gs_lds[base[j] + i];
+        return ld_word(chunk[j], i);
+    }
+
+    __device__ __forceinline__ void advance(const Arcs<K> &arc, int j)
+    {
+        if (!WIRES && LDSRC) {
+            // an LDS read past the lane's words stays inside the LDS
+            // allocation or returns 0, so it needs no branch
+            const int32_t v = word(j, idx[j]);
+            a[j] = idx[j] < end[j] ? v : kInf;
+            return;
+        }
+        if (!WIRES) {
+            a[j] = idx[j] < end[j] ? word(j, idx[j]) : kInf;
+            return;
+        }
+        const int pv = (state >> j) & 1;
+        for (;;) {
+            if (idx[j] >= end[j]) {
+                a[j] = kInf;
+                return;
+            }
+            const int32_t e0 = word(j, idx[j]);
+            const int32_t d = pv ? arc.wf[j] : arc.wr[j];   // the net edge goes to !pv
+            if (idx[j] + 1 < end[j] && word(j, idx[j] + 1) - e0 < d) {
+                idx[j] += 2;                                // pulse narrower than the wire delay
+                continue;
+            }
+            a[j] = e0 + d;
+            return;
+        }
+    }
+};
+
 // Lookup table of a gate with up to three pins, one entry per (pin state
 // after an event, mask of the pins that switched): bit 0 = the truth-table
 // output, bits 1.. = the smallest arc delay of the switched pins for that
 // output edge.  64 words per wave in LDS, built by the 64 lanes at once.
-template <int K, bool WIRES>
-__device__ __forceinline__ void build_lut(const Pins<K, WIRES> &P, uint64_t truth, int lane, uint32_t lut_base)
+template <int K>
+__device__ __forceinline__ void build_lut(const Arcs<K> &arc, uint64_t truth, int lane, uint32_t lut_base)
 {
     const uint32_t st = (uint32_t)lane >> 3, m = (uint32_t)lane & 7u;
     const int y = (int)((truth >> st) & 1);
     int32_t d = kInf >> 1;
 #pragma unroll
     for (int j = 0; j < K; j++) {
-        const int32_t sel = -(int32_t)((st >> P.q[j]) & 1);
-        const int32_t rise = P.r0[j] + (sel & (P.r1[j] - P.r0[j]));
-        const int32_t fall = P.f0[j] + (sel & (P.f1[j] - P.f0[j]));
+        const int32_t sel = -(int32_t)((st >> arc.q[j]) & 1);
+        const int32_t rise = arc.r0[j] + (sel & (arc.r1[j] - arc.r0[j]));
+        const int32_t fall = arc.f0[j] + (sel & (arc.f1[j] - arc.f0[j]));
         const int32_t dj = fall + ((-y) & (rise - fall));
         const int32_t mj = -(int32_t)((m >> j) & 1);
         d = min(d, (dj & mj) | ((kInf >> 1) & ~mj));
@@ -470,13 +501,13 @@ __device__ __forceinline__ void build_lut(const Pins<K, WIRES> &P, uint64_t trut
 // stages output edges in LDS (at most CAP per lane); MODE 1 writes them to
 // dst[0 .. keep) in global memory (entries at or beyond `keep` are retracted
 // before the walk ends, so they are not stored).
-template <int K, bool WIRES, int MODE, int CAP>
-__device__ __forceinline__ void walk(Pins<K, WIRES> &P, uint64_t truth, int32_t T, int z, uint32_t lut_base,
-                                     uint32_t out_lane, int32_t *dst, int32_t keep, int32_t &cnt_out,
-                                     int32_t &acc_out, int32_t &z_out)
+template <int K, bool WIRES, bool LDSRC, int MODE, int CAP>
+__device__ __forceinline__ void walk(Cursor<K, WIRES, LDSRC> &P, const Arcs<K> &arc, uint64_t truth, int32_t T,
+                                     int z, uint32_t lut_base, uint32_t out_lane, int32_t *dst, int32_t keep,
+                                     int32_t &cnt_out, int32_t &acc_out, int32_t &z_out)
 {
 #pragma unroll
-    for (int j = 0; j < K; j++) P.advance(j);
+    for (int j = 0; j < K; j++) P.advance(arc, j);
     int32_t W = 0, Wp = 0, cnt = 0, acc = 0;
     for (;;) {
         int32_t t = P.a[0];
@@ -490,7 +521,7 @@ __device__ __forceinline__ void walk(Pins<K, WIRES> &P, uint64_t truth, int32_t 
                 sw |= 1u << j;
                 P.state ^= 1u << j;             // the wire filter reads the pin's new value
                 P.idx[j]++;
-                P.advance(j);
+                P.advance(arc, j);
             }
         }
         int y;
@@ -504,7 +535,7 @@ __device__ __forceinline__ void walk(Pins<K, WIRES> &P, uint64_t truth, int32_t 
             d = 0;
         }
         if (y != z) {
-            if (K > 3) d = P.delay(sw, y);
+            if (K > 3) d = arc.delay(P.state, sw, y);
             const bool retract = t < W;
             const int32_t e = retract ? W : t + d;
             const int32_t ce = min(e, T);
@@ -531,17 +562,23 @@ __device__ __forceinline__ void walk(Pins<K, WIRES> &P, uint64_t truth, int32_t 
 }
 
 // One gate over `ntl` consecutive tiles starting at tile0 (one lane per
-// cycle of a tile).  The per-gate work (arc data, delay table) is done once;
-// SAIF counts of the output net are summed over the tiles and added with one
-// atomic per counter.
+// cycle of a tile).  The per-gate work (arc data, delay table) is done once.
+// Tiles are processed in groups of GT: lane c = j * GT + u fetches the
+// header and the edge total of pin j's chunk in tile u of the group, every
+// lane fetches its own lane ends of all the group's chunks, and the group's
+// fanin words are then copied into LDS, so that the walks read no global
+// memory (groups too large for the staging area walk the arena instead).
+// SAIF counts of the output net are summed over the tiles and added with
+// one atomic per counter.
 template <int K, bool WIRES, int CAP, bool REMAP>
 __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint32_t tile0, uint32_t ntl, int lane,
-                                          uint32_t lut_base, uint32_t out_base)
+                                          uint32_t lut_base, uint32_t out_base, uint32_t stage_base)
 {
+    constexpr uint32_t GT = K <= 3 ? 4 : 2;
     const WinView &win = sg.win;
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;
-    Pins<K, WIRES> P;
+    Arcs<K> arc;
     // chunk row of every fanin and of the output: the net id, or its slot
     // in the re-simulated cone (REMAP; then rd_* marks a resident chunk)
     uint32_t row[K];
@@ -558,118 +595,205 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             resident[j] = sl < 0;
             row[j] = sl < 0 ? (uint32_t)pr.net : (uint32_t)sl;
         }
-        P.q[j] = pr.q; P.r0[j] = pr.r0; P.f0[j] = pr.f0; P.r1[j] = pr.r1; P.f1[j] = pr.f1;
-        P.wr[j] = pr.wr; P.wf[j] = pr.wf;
+        arc.q[j] = pr.q; arc.r0[j] = pr.r0; arc.f0[j] = pr.f0; arc.r1[j] = pr.r1; arc.f1[j] = pr.f1;
+        arc.wr[j] = pr.wr; arc.wf[j] = pr.wf;
     }
     if (K <= 3) {
-        build_lut<K, WIRES>(P, g.truth, lane, lut_base);
+        build_lut<K>(arc, g.truth, lane, lut_base);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // One arena reservation for all tiles of the wave, issued before any
-    // walk so that its latency overlaps the work: a lane's output never has
-    // more edges than its pins have events, so the fanin chunk sizes bound
-    // the output chunks (Algorithm 1 appends at most one edge per event).
-    uint32_t bound = 0;
-    for (uint32_t tt = 0; tt < ntl; tt++) {
+    // the chunk this lane fetches the header of
+    const uint32_t cj = (uint32_t)lane / GT, cu = (uint32_t)lane % GT;
+    uint32_t crow = 0;
+    bool cres = false;
 #pragma unroll
-        for (int j = 0; j < K; j++) {
-            const uint16_t *esrc = (REMAP && resident[j]) ? win.rd_ends : win.ends;
-            bound += chunk_total(esrc, (uint64_t)row[j] * ntile + tile0 + tt);
+    for (int j = 0; j < K; j++) {
+        if (cj == (uint32_t)j) {
+            crow = row[j];
+            cres = resident[j];
         }
     }
-    uint64_t wbase = 0;
-    bool wok = true;
-    if (bound > 0) {
-        const uint32_t stripe = (blockIdx.x + sg.salt) & win.stripe_mask;
-        uint64_t b = 0;
-        if (lane == 0)
-            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)bound,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        b = uniform64(b);
-        if (b + bound > win.slice_words) {
-            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            wok = false;
-        }
-        wbase = win.arena_off + (uint64_t)stripe * win.slice_words + b;
-    }
-    uint64_t used = 0;
+    const ChunkHdr *chsrc = (REMAP && cres) ? win.rd_hdr : win.hdr;
+    const uint16_t *cesrc = (REMAP && cres) ? win.rd_ends : win.ends;
+
     const uint32_t out_lane = out_base + lane;
     uint32_t tc_sum = 0, nact_sum = 0;
     int32_t t1_lane = 0;
-    for (uint32_t tt = 0; tt < ntl; tt++) {
-        const uint32_t tile = tile0 + tt;
-        const int32_t lc = (int32_t)(tile * kLanes) + lane;
-        const bool active = lc < win.n_cycles;
-        uint32_t idx0[K];
-        uint32_t state0 = 0;
+    for (uint32_t gb = 0; gb < ntl; gb += GT) {
+        const uint32_t ng = min(GT, ntl - gb);
+        // Every load below is issued by every lane (lanes without a chunk of
+        // their own, and tiles past a ragged group's end, read the group's
+        // last chunk again), so that the wait for the first of them does not
+        // have to cover the others.
+        const bool cval = cj < (uint32_t)K && cu < ng;
+        const uint64_t cci = (uint64_t)crow * ntile + tile0 + gb + min(cu, ng - 1);
+        const ChunkHdr ch = *glob(chsrc + cci);
+        const uint32_t c_tot = cval ? (uint32_t)*glob(cesrc + cci * kLanes + kLanes - 1) : 0u;
+        const uint64_t c_off = ch.off, c_mask = ch.mask;
+        uint32_t ev[K][GT];
 #pragma unroll
         for (int j = 0; j < K; j++) {
-            const uint64_t ci = (uint64_t)row[j] * ntile + tile;
-            const ChunkHdr *hsrc = win.hdr;
-            const uint16_t *esrc = win.ends;
-            if (REMAP && resident[j]) {
-                hsrc = win.rd_hdr;
-                esrc = win.rd_ends;
-            }
-            const ChunkHdr h = *kons(hsrc + ci);
-            const uint32_t e = *glob(esrc + ci * kLanes + lane);
-            const uint32_t lo = wave_shr1(e);
-            P.chunk[j] = win.times + h.off;
-            P.idx[j] = idx0[j] = active ? lo : 0u;
-            P.end[j] = active ? e : 0u;
-            state0 |= (uint32_t)((h.mask >> lane) & 1) << j;
-        }
-        P.state = state0;
-        const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
-        int32_t cnt, acc, z;
-        walk<K, WIRES, 0, CAP>(P, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
-
-        const uint32_t ucnt = (uint32_t)cnt;
-        const uint32_t incl = wave_incl_scan(ucnt);
-        const uint32_t total = (uint32_t)lane63(incl);
-        const uint64_t mask = __ballot(active && y0);
-        const uint64_t ci = (uint64_t)out_row * ntile + tile;
-        bool ok = wok;
-        if (total > kMaxChunk) {
-            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-        }
-        if (used + total > bound) {                    // cannot happen (bound above); never write past it
-            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-        }
-        const uint64_t base = wbase + used;
-        if (ok) used += total;
-        *glob(win.ends + ci * kLanes + lane) = ok ? (uint16_t)incl : (uint16_t)0;
-        if (lane == 0) {
-            ChunkHdr h;
-            h.off = ok ? base : 0;
-            h.mask = mask;
-            *glob(win.hdr + ci) = h;
-        }
-        if (ok) {
-            int32_t *out = win.times + base + (incl - ucnt);
-            const int32_t n = cnt < CAP ? cnt : CAP;
-            for (int32_t i = 0; i < n; i++) *glob(out + i) = gs_lds[out_lane + i * kLanes];
-            const uint64_t spill = __ballot(cnt > CAP);
-            if (spill) {
-                if (cnt > CAP) {
+            const uint16_t *esrc = (REMAP && resident[j]) ? win.rd_ends : win.ends;
 #pragma unroll
-                    for (int j = 0; j < K; j++) P.idx[j] = idx0[j];
-                    P.state = state0;
-                    int32_t c2, a2, z2;
-                    walk<K, WIRES, 1, CAP>(P, g.truth, T, y0, lut_base, 0, out, cnt, c2, a2, z2);
+            for (uint32_t u = 0; u < GT; u++)
+                ev[j][u] = *glob(esrc + ((uint64_t)row[j] * ntile + tile0 + gb + min(u, ng - 1)) * kLanes + lane);
+        }
+        // The group's output chunks get one arena reservation: a lane's
+        // output never has more edges than its pins have events (Algorithm 1
+        // appends at most one edge per event), so the fanin totals bound it.
+        const uint32_t c_incl = wave_incl_scan(c_tot);
+        const uint32_t bound = (uint32_t)lane63(c_incl);
+        const uint32_t c_pos = stage_base + c_incl - c_tot;     // chunk's first word in the LDS stage
+        // (the returned offset is first needed after the walk of the first tile)
+        const uint32_t stripe = (blockIdx.x + sg.salt) & win.stripe_mask;
+        uint64_t bres = 0;
+        if (bound > 0 && lane == 0)
+            bres = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)bound,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t wbase = 0;
+        bool wok = true, placed = false;
+        const bool staged = bound <= kStageWords;
+        if (staged && bound > 0) {
+            // copy every chunk's words into the stage: the first 64 words of
+            // all chunks with one batch of loads, longer chunks row by row
+            int32_t v[K * GT];
+#pragma unroll
+            for (uint32_t c = 0; c < K * GT; c++) {
+                const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)c_tot, (int)c);
+                const uint64_t off = readlane64(c_off, c);
+                v[c] = 0;
+                if ((uint32_t)lane < n) v[c] = ld_word(win.times + off, (uint32_t)lane);
+            }
+#pragma unroll
+            for (uint32_t c = 0; c < K * GT; c++) {
+                const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)c_tot, (int)c);
+                const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (int)c);
+                if ((uint32_t)lane < n) gs_lds[p + lane] = v[c];
+            }
+            if (__ballot(c_tot > (uint32_t)kLanes)) {
+                for (uint32_t c = 0; c < K * GT; c++) {
+                    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)c_tot, (int)c);
+                    const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (int)c);
+                    const uint64_t off = readlane64(c_off, c);
+                    for (uint32_t r = kLanes + lane; r < n; r += kLanes) gs_lds[p + r] = ld_word(win.times + off, r);
                 }
-                if (lane == 0)
-                    __hip_atomic_fetch_add(glob(win.flags + 2), (unsigned int)__popcll(spill), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        uint64_t used = 0;
+        for (uint32_t u = 0; u < ng; u++) {
+            const uint32_t tile = tile0 + gb + u;
+            const int32_t lc = (int32_t)(tile * kLanes) + lane;
+            const bool active = lc < win.n_cycles;
+            uint32_t lo[K], hi[K], base[K];
+            const int32_t *chunk[K];
+            uint32_t state0 = 0;
+#pragma unroll
+            for (int j = 0; j < K; j++) {
+                const uint32_t c = (uint32_t)j * GT + u;
+                const uint64_t mask = readlane64(c_mask, c);
+                base[j] = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (int)c);
+                chunk[j] = win.times + readlane64(c_off, c);
+                const uint32_t e = ev[j][0];
+                const uint32_t l = wave_shr1(e);
+                lo[j] = active ? l : 0u;
+                hi[j] = active ? e : 0u;
+                state0 |= (uint32_t)((mask >> lane) & 1) << j;
+            }
+            const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
+            int32_t cnt, acc, z;
+            if (staged) {
+                Cursor<K, WIRES, true> P;
+#pragma unroll
+                for (int j = 0; j < K; j++) {
+                    P.base[j] = base[j];
+                    P.idx[j] = lo[j];
+                    P.end[j] = hi[j];
+                }
+                P.state = state0;
+                walk<K, WIRES, true, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
+            } else {
+                Cursor<K, WIRES, false> P;
+#pragma unroll
+                for (int j = 0; j < K; j++) {
+                    P.chunk[j] = chunk[j];
+                    P.idx[j] = lo[j];
+                    P.end[j] = hi[j];
+                }
+                P.state = state0;
+                walk<K, WIRES, false, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
+            }
+
+            if (!placed) {
+                placed = true;
+                const uint64_t b = uniform64(bres);
+                if (bound > 0 && b + bound > win.slice_words) {
+                    if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    wok = false;
+                }
+                wbase = win.arena_off + (uint64_t)stripe * win.slice_words + b;
+            }
+            const uint32_t ucnt = (uint32_t)cnt;
+            const uint32_t incl = wave_incl_scan(ucnt);
+            const uint32_t total = (uint32_t)lane63(incl);
+            const uint64_t mask = __ballot(active && y0);
+            const uint64_t ci = (uint64_t)out_row * ntile + tile;
+            bool ok = wok;
+            if (total > kMaxChunk) {
+                if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+            }
+            if (used + total > bound) {                    // cannot happen (bound above); never write past it
+                if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+            }
+            const uint64_t obase = wbase + used;
+            if (ok) used += total;
+            *glob(win.ends + ci * kLanes + lane) = ok ? (uint16_t)incl : (uint16_t)0;
+            if (lane == 0) {
+                ChunkHdr h;
+                h.off = ok ? obase : 0;
+                h.mask = mask;
+                *glob(win.hdr + ci) = h;
+            }
+            if (ok) {
+                int32_t *out = win.times + obase + (incl - ucnt);
+                const int32_t n = cnt < CAP ? cnt : CAP;
+                for (int32_t i = 0; i < n; i++) *glob(out + i) = gs_lds[out_lane + i * kLanes];
+                const uint64_t spill = __ballot(cnt > CAP);
+                if (spill) {
+                    // lanes whose list outgrew the staging walk again, from the
+                    // arena, writing to their place in the output chunk
+                    if (cnt > CAP) {
+                        Cursor<K, WIRES, false> P;
+#pragma unroll
+                        for (int j = 0; j < K; j++) {
+                            P.chunk[j] = chunk[j];
+                            P.idx[j] = lo[j];
+                            P.end[j] = hi[j];
+                        }
+                        P.state = state0;
+                        int32_t c2, a2, z2;
+                        walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, cnt, c2, a2, z2);
+                    }
+                    if (lane == 0)
+                        __hip_atomic_fetch_add(glob(win.flags + 2), (unsigned int)__popcll(spill), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            tc_sum += total;
+            nact_sum += (uint32_t)__popcll(__ballot(active));
+            t1_lane += active ? z * T + acc : 0;
+#pragma unroll
+            for (int j = 0; j < K; j++) {
+#pragma unroll
+                for (uint32_t k = 0; k + 1 < GT; k++) ev[j][k] = ev[j][k + 1];
             }
         }
-        tc_sum += total;
-        nact_sum += (uint32_t)__popcll(__ballot(active));
-        t1_lane += active ? z * T + acc : 0;
     }
     const int32_t sum1 = lane63(wave_incl_scan((uint32_t)t1_lane));
     if (lane == 0) {
@@ -694,7 +818,8 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int n, uin
 }
 
 // Wave w of a launch -> (segment, gate, group of tpw consecutive tiles).
-// LDS per wave: 64 words of delay table, then CAP x 64 staged output words.
+// LDS per wave: 64 words of delay table, CAP x 64 staged output words, then
+// the staged fanin words.
 template <bool WIRES, int CAP, int KMAX, bool REMAP>
 __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ segs, int32_t n_segs, uint64_t n_waves,
                                                         uint32_t tpw)
@@ -705,7 +830,10 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const uint64_t w = (uint64_t)blockIdx.x * wpb + wib;
     if (w >= n_waves) return;
     const int si = n_segs == 1 ? 0 : find_seg(segs, n_segs, w);
-    const Seg &sg = segs[si];
+    // a private copy read through the constant address space: the segment
+    // table is never written by the launch, so its fields load with s_load
+    // and need not be reloaded after the kernel's own stores
+    const Seg sg = *kons(segs + si);
     const uint32_t local = (uint32_t)(w - sg.wave_begin);
     const uint32_t ntile = (uint32_t)sg.win.n_tiles;
     const uint32_t ngroup = (ntile + tpw - 1) / tpw;
@@ -714,15 +842,16 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const uint32_t tile0 = grp * tpw;
     const uint32_t ntl = min(tpw, ntile - tile0);
     const GateRec g = *kons(sg.gates + sg.gate_begin + gi);
-    const uint32_t lut_base = wib * (kLanes + CAP * kLanes);
+    const uint32_t lut_base = wib * (kLanes + CAP * kLanes + kStageWords);
     const uint32_t out_base = lut_base + kLanes;
+    const uint32_t stage_base = out_base + CAP * kLanes;
     switch (g.k) {
-    case 1: eval_gate<1, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 2: eval_gate<2, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 3: eval_gate<3, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
-    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base); break;
+    case 1: eval_gate<1, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 2: eval_gate<2, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 3: eval_gate<3, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
     default: break;
     }
 }
@@ -732,7 +861,7 @@ static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
                             hipStream_t s)
 {
     const uint64_t blocks = (n_waves + wpb - 1) / wpb;
-    const size_t lds = (size_t)wpb * ((size_t)cap * kLanes + kLanes) * sizeof(int32_t);
+    const size_t lds = (size_t)wpb * ((size_t)cap * kLanes + kLanes + kStageWords) * sizeof(int32_t);
     const dim3 grid((unsigned)blocks), block(kLanes * wpb);
     switch (cap) {
     case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgatesim.so")
+# GATESIM_LIBRARY names another build of the same library (same ABI)
+LIB_PATH = os.environ.get("GATESIM_LIBRARY") or os.path.join(_HERE, "libgatesim.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
