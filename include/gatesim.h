@@ -77,7 +77,7 @@ typedef struct {
     uint64_t hbm_budget;      /* bytes of device memory the context may hold for waveforms; 0 = 80% of free memory */
     void    *arena;           /* optional caller-owned device buffer used for all waveform storage */
     uint64_t arena_bytes;
-    int32_t  window_cycles;   /* cycles per window; 0 = as many as fit the budget, capped at 4096 */
+    int32_t  window_cycles;   /* cycles per window; 0 = as many as fit the budget, capped at 16384 */
     int32_t  lds_cap;         /* transitions per (net, cycle) staged on chip before the spill path: 4, 8, 16 or 32; 0 = 8 */
     int32_t  waves_per_block; /* 1, 2, 4 or 8; 0 = 4 */
     int32_t  schedule;        /* GS_SCHED_LEVELS or GS_SCHED_GRAPH */

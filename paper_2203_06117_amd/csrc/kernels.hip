@@ -95,42 +95,6 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Places a wave's finished chunk: one atomic bump of the transition arena
-// for the whole wave, then lane ends and the chunk header.  Returns false
-// (and writes an empty, in-bounds chunk) when the arena is full or the chunk
-// exceeds 16-bit lane ends; the host then redoes the window.
-__device__ __forceinline__ bool place_chunk(const WinView &win, uint64_t ci, uint32_t incl, uint32_t total,
-                                            uint64_t mask, int lane, uint32_t salt, uint64_t &base)
-{
-    bool ok = true;
-    if (total > kMaxChunk) {
-        if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = false;
-    }
-    uint64_t b = 0;
-    if (ok && total > 0) {
-        const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
-        if (lane == 0)
-            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)total,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        b = uniform64(b);
-        if (b + total > win.slice_words) {
-            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-        }
-        b += win.arena_off + (uint64_t)stripe * win.slice_words;
-    }
-    *glob(win.ends + ci * kLanes + lane) = ok ? (uint16_t)incl : (uint16_t)0;
-    if (lane == 0) {
-        ChunkHdr h;
-        h.off = ok ? b : 0;
-        h.mask = mask;
-        *glob(win.hdr + ci) = h;
-    }
-    base = b;
-    return ok;
-}
-
 // --------------------------------------------------------------------------
 // small utility kernels (also used instead of memset so that every launch
 // sequence can be captured into a graph)
@@ -285,6 +249,12 @@ __device__ __forceinline__ int64_t lower_bound64(const int64_t *__restrict__ a, 
     return lo;
 }
 
+// Tiles an expansion wave handles: the chunks of one input in an aligned
+// group of this many tiles are placed one after another in the arena, as
+// gate evaluation places its output chunks, so that a consumer can copy a
+// pin's group of chunks as one range.
+constexpr uint32_t kExpandGroup = 4;
+
 __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0_p,
                                                      uint32_t salt, uint64_t n_waves)
 {
@@ -294,55 +264,113 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + wib;
     if (w >= n_waves) return;
     const uint32_t ntile = (uint32_t)win.n_tiles;
-    const uint32_t i = uniform((uint32_t)(w / ntile));
-    const uint32_t tile = uniform((uint32_t)(w % ntile));
-    const int32_t lc = (int32_t)(tile * kLanes + lane);
-    const bool active = lc < win.n_cycles;
+    const uint32_t ngrp = (ntile + kExpandGroup - 1) / kExpandGroup;
+    const uint32_t i = uniform((uint32_t)(w / ngrp));
+    const uint32_t t0 = uniform((uint32_t)(w % ngrp)) * kExpandGroup;
+    const uint32_t nt = min(kExpandGroup, ntile - t0);
     const int64_t T = st.period;
-    const int64_t c0 = (int64_t)(cycle0 + lc) * T;
     const int64_t lo = *kons(st.toggle_ptr + i), hi = *kons(st.toggle_ptr + i + 1);
-    // the tile's toggles first (wave-uniform search), then each lane's
-    // cycle inside that short range
-    const int64_t tile_t0 = (int64_t)(cycle0 + (int32_t)(tile * kLanes)) * T;
-    int64_t ta = lo, tb = hi;
-    while (ta < tb) {
-        const int64_t mid = (ta + tb) >> 1;
-        if (*kons(st.toggle_ps + mid) < tile_t0) ta = mid + 1;
-        else tb = mid;
+    // each lane's toggle range [s, s + cnt) in every tile of the group: the
+    // tile's toggles first (wave-uniform search), then the lane's cycle
+    // inside that short range
+    int64_t s[kExpandGroup];
+    uint32_t cnt[kExpandGroup], incl[kExpandGroup], total[kExpandGroup];
+    uint64_t mask[kExpandGroup];
+    uint32_t bound = 0;
+    int64_t ta = lo;
+#pragma unroll
+    for (uint32_t u = 0; u < kExpandGroup; u++) {
+        s[u] = 0;
+        cnt[u] = 0;
+        incl[u] = 0;
+        total[u] = 0;
+        mask[u] = 0;
+        if (u >= nt) continue;
+        const uint32_t tile = t0 + u;
+        const int32_t lc = (int32_t)(tile * kLanes + lane);
+        const bool active = lc < win.n_cycles;
+        const int64_t c0 = (int64_t)(cycle0 + lc) * T;
+        const int64_t tile_t0 = (int64_t)(cycle0 + (int32_t)(tile * kLanes)) * T;
+        int64_t tb = hi;
+        while (ta < tb) {
+            const int64_t mid = (ta + tb) >> 1;
+            if (*kons(st.toggle_ps + mid) < tile_t0) ta = mid + 1;
+            else tb = mid;
+        }
+        int64_t tz = ta;
+        tb = hi;
+        while (tz < tb) {
+            const int64_t mid = (tz + tb) >> 1;
+            if (*kons(st.toggle_ps + mid) < tile_t0 + kLanes * T) tz = mid + 1;
+            else tb = mid;
+        }
+        int64_t a = 0, e = 0;
+        if (active) {
+            a = lower_bound64(st.toggle_ps, ta, tz, c0);
+            e = lower_bound64(st.toggle_ps, a, tz, c0 + T);
+        }
+        s[u] = a;
+        cnt[u] = (uint32_t)(e - a);
+        const int v0 = active ? (int)((*kons(st.init + i) + (uint64_t)(a - lo)) & 1) : 0;
+        incl[u] = wave_incl_scan(cnt[u]);
+        total[u] = (uint32_t)lane63(incl[u]);
+        mask[u] = __ballot(v0 != 0);
+        bound += total[u];
+        ta = tz;
     }
-    int64_t tz = ta;
-    tb = hi;
-    while (tz < tb) {
-        const int64_t mid = (tz + tb) >> 1;
-        if (*kons(st.toggle_ps + mid) < tile_t0 + kLanes * T) tz = mid + 1;
-        else tb = mid;
+    // one arena reservation for the group's chunks
+    const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
+    uint64_t b = 0;
+    bool ok = true;
+    if (bound > 0) {
+        if (lane == 0)
+            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)bound,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b = uniform64(b);
+        if (b + bound > win.slice_words) {
+            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+        }
     }
-    int64_t s = 0, e = 0;
-    if (active) {
-        s = lower_bound64(st.toggle_ps, ta, tz, c0);
-        e = lower_bound64(st.toggle_ps, s, tz, c0 + T);
+    uint64_t base = win.arena_off + (uint64_t)stripe * win.slice_words + b;
+    uint32_t tc = 0, nact = 0;
+    int32_t t1_lane = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kExpandGroup; u++) {
+        if (u >= nt) continue;
+        const uint32_t tile = t0 + u;
+        const int32_t lc = (int32_t)(tile * kLanes + lane);
+        const bool active = lc < win.n_cycles;
+        const int64_t c0 = (int64_t)(cycle0 + lc) * T;
+        bool okc = ok;
+        if (total[u] > kMaxChunk) {
+            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            okc = false;
+        }
+        const uint64_t ci = (uint64_t)i * ntile + tile;
+        *glob(win.ends + ci * kLanes + lane) = okc ? (uint16_t)incl[u] : (uint16_t)0;
+        if (lane == 0) {
+            ChunkHdr h;
+            h.off = okc ? base : 0;
+            h.mask = mask[u];
+            *glob(win.hdr + ci) = h;
+        }
+        // time at 1 inside [0, T): final value * T - rising-edge times + falling-edge times
+        int v = (int)((mask[u] >> lane) & 1), acc1 = 0;
+        for (uint32_t j = 0; j < cnt[u]; j++) {
+            const int32_t tl = (int32_t)(st.toggle_ps[s[u] + j] - c0);
+            if (okc) *glob(win.times + base + (incl[u] - cnt[u]) + j) = tl;
+            v ^= 1;
+            acc1 += v ? -tl : tl;
+        }
+        base += total[u];
+        tc += total[u];
+        nact += (uint32_t)__popcll(__ballot(active));
+        t1_lane += active ? v * (int32_t)T + acc1 : 0;
     }
-    const uint32_t cnt = (uint32_t)(e - s);
-    const int v0 = active ? (int)((*kons(st.init + i) + (uint64_t)(s - lo)) & 1) : 0;
-    const uint32_t incl = wave_incl_scan(cnt);
-    const uint32_t total = (uint32_t)lane63(incl);
-    const uint64_t mask = __ballot(v0 != 0);
-    const uint64_t ci = (uint64_t)i * ntile + tile;
-    uint64_t base;
-    const bool ok = place_chunk(win, ci, incl, total, mask, lane, salt, base);
-    // time at 1 inside [0, T): final value * T - sum of rising-edge times + sum of falling-edge times
-    int v = v0, a = 0;
-    for (uint32_t j = 0; j < cnt; j++) {
-        int32_t tl = (int32_t)(st.toggle_ps[s + j] - c0);
-        if (ok) *glob(win.times + base + (incl - cnt) + j) = tl;
-        v ^= 1;
-        a += v ? -tl : tl;
-    }
-    const int32_t t1 = active ? v * (int32_t)T + a : 0;
-    const int32_t sum1 = lane63(wave_incl_scan((uint32_t)t1));
-    const uint32_t nact = (uint32_t)__popcll(__ballot(active));
+    const int32_t sum1 = lane63(wave_incl_scan((uint32_t)t1_lane));
     if (lane == 0) {
-        __hip_atomic_fetch_add(glob(acc.tc + i), (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(glob(acc.tc + i), (unsigned long long)tc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(acc.t1 + i), (unsigned long long)(int64_t)sum1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(acc.t0 + i), (unsigned long long)((int64_t)nact * T - sum1), __ATOMIC_RELAXED,
@@ -352,7 +380,7 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
 
 hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0, uint32_t salt, hipStream_t s)
 {
-    uint64_t n_waves = (uint64_t)st.n_inputs * (uint64_t)win.n_tiles;
+    uint64_t n_waves = (uint64_t)st.n_inputs * (uint64_t)((win.n_tiles + kExpandGroup - 1) / kExpandGroup);
     if (n_waves == 0) return hipSuccess;
     const int wpb = 4;
     uint64_t blocks = (n_waves + wpb - 1) / wpb;
@@ -391,6 +419,12 @@ constexpr uint32_t kStageWords = 512;
 __device__ __forceinline__ int32_t ld_word(const int32_t *chunk, uint32_t idx)
 {
     return *(const GAS int32_t *)((const GAS char *)glob(chunk) + (uint64_t)(idx << 2));
+}
+
+// base[idx] for a wave-uniform base (scalar base + 32-bit vector offset)
+__device__ __forceinline__ uint32_t ld_u16(const uint16_t *base, uint32_t idx)
+{
+    return *(const GAS uint16_t *)((const GAS char *)glob(base) + (uint64_t)(idx << 1));
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l)
@@ -561,6 +595,65 @@ __device__ __forceinline__ void walk(Cursor<K, WIRES, LDSRC> &P, const Arcs<K> &
     z_out = z;
 }
 
+// The event loop of `walk` for fanin words staged in LDS without
+// interconnect delays, written without branches: every pin's next word and
+// every state update is computed for all lanes and selected, so that a
+// lane's event costs the same straight-line code whichever pins switch and
+// whether the output edge is appended, cancelled or not needed.  Output
+// edges go to LDS slot min(cnt, CAP); slot CAP is a spare that absorbs the
+// stores of steps that append nothing and of lanes past CAP.
+template <int K, int CAP>
+__device__ __forceinline__ void walk_lds(Cursor<K, false, true> &P, const Arcs<K> &arc, uint64_t truth, int32_t T,
+                                         int z, uint32_t lut_base, uint32_t out_lane, int32_t &cnt_out)
+{
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+        const int32_t v = gs_lds[P.base[j] + P.idx[j]];
+        P.a[j] = P.idx[j] < P.end[j] ? v : kInf;
+    }
+    int32_t W = 0, Wp = 0, cnt = 0;
+    for (;;) {
+        int32_t t = P.a[0];
+#pragma unroll
+        for (int j = 1; j < K; j++) t = min(t, P.a[j]);
+        if (t == kInf) break;
+        uint32_t sw = 0;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const uint32_t m = P.a[j] == t ? 1u : 0u;
+            sw |= m << j;
+            P.idx[j] += m;
+        }
+        P.state ^= sw;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const int32_t v = gs_lds[P.base[j] + P.idx[j]];
+            P.a[j] = P.idx[j] < P.end[j] ? v : kInf;
+        }
+        int y;
+        int32_t d;
+        if (K <= 3) {
+            const int32_t ent = gs_lds[lut_base + ((P.state << 3) | sw)];
+            y = ent & 1;
+            d = ent >> 1;
+        } else {
+            y = (int)((truth >> P.state) & 1);
+            d = arc.delay(P.state, sw, y);
+        }
+        const bool chg = y != z;
+        const bool retract = t < W;
+        const int32_t td = t + d;
+        gs_lds[out_lane + min(cnt, CAP) * kLanes] = td;
+        const bool app = chg && !retract;
+        cnt += app ? 1 : (chg ? -1 : 0);
+        const int32_t W0 = W;
+        W = app ? td : (chg ? Wp : W);
+        Wp = app ? W0 : Wp;
+        z = y;
+    }
+    cnt_out = cnt;
+}
+
 // One gate over `ntl` consecutive tiles starting at tile0 (one lane per
 // cycle of a tile).  The per-gate work (arc data, delay table) is done once.
 // Tiles are processed in groups of GT: lane c = j * GT + u fetches the
@@ -632,13 +725,17 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         const ChunkHdr ch = *glob(chsrc + cci);
         const uint32_t c_tot = cval ? (uint32_t)*glob(cesrc + cci * kLanes + kLanes - 1) : 0u;
         const uint64_t c_off = ch.off, c_mask = ch.mask;
-        uint32_t ev[K][GT];
+        // lane ends of pin j in tiles u and u+1 of the group share one word
+        uint32_t ev[K][GT / 2];
 #pragma unroll
         for (int j = 0; j < K; j++) {
             const uint16_t *esrc = (REMAP && resident[j]) ? win.rd_ends : win.ends;
 #pragma unroll
-            for (uint32_t u = 0; u < GT; u++)
-                ev[j][u] = *glob(esrc + ((uint64_t)row[j] * ntile + tile0 + gb + min(u, ng - 1)) * kLanes + lane);
+            for (uint32_t u = 0; u < GT; u += 2) {
+                const uint16_t *r0 = esrc + ((uint64_t)row[j] * ntile + tile0 + gb + min(u, ng - 1)) * kLanes;
+                const uint16_t *r1 = esrc + ((uint64_t)row[j] * ntile + tile0 + gb + min(u + 1, ng - 1)) * kLanes;
+                ev[j][u / 2] = ld_u16(r0, (uint32_t)lane) | (ld_u16(r1, (uint32_t)lane) << 16);
+            }
         }
         // The group's output chunks get one arena reservation: a lane's
         // output never has more edges than its pins have events (Algorithm 1
@@ -655,30 +752,52 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         uint64_t wbase = 0;
         bool wok = true, placed = false;
         const bool staged = bound <= kStageWords;
-        if (staged && bound > 0) {
-            // copy every chunk's words into the stage: the first 64 words of
-            // all chunks with one batch of loads, longer chunks row by row
-            int32_t v[K * GT];
+        // A producing wave places the chunks of its tile group one after
+        // another, so a pin's chunks in this group are usually one
+        // contiguous range of the arena, and the stage keeps them in the same
+        // order: then each pin is copied as one range.
+        const uint32_t nlo = dpp0<0x101>((uint32_t)c_off), nhi = dpp0<0x101>((uint32_t)(c_off >> 32));   // row_shl:1
+        const bool gap = cval && cu + 1 < ng && c_off + c_tot != (((uint64_t)nhi << 32) | nlo);
+        const bool runs = __ballot(gap) == 0;
+        if (staged && bound > 0 && runs) {
+            uint32_t pin_pos[K], pin_n[K];
 #pragma unroll
-            for (uint32_t c = 0; c < K * GT; c++) {
-                const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)c_tot, (int)c);
-                const uint64_t off = readlane64(c_off, c);
-                v[c] = 0;
-                if ((uint32_t)lane < n) v[c] = ld_word(win.times + off, (uint32_t)lane);
+            for (int j = 0; j < K; j++) {
+                pin_pos[j] = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, j * (int)GT);
+                const uint32_t pend = j + 1 < K ? (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (j + 1) * (int)GT)
+                                                : stage_base + bound;
+                pin_n[j] = pend - pin_pos[j];
+            }
+            int32_t v0[K], v1[K];
+#pragma unroll
+            for (int j = 0; j < K; j++) {
+                const int32_t *src = win.times + readlane64(c_off, (uint32_t)j * GT);
+                v0[j] = (uint32_t)lane < pin_n[j] ? ld_word(src, (uint32_t)lane) : 0;
+                v1[j] = (uint32_t)lane + kLanes < pin_n[j] ? ld_word(src, (uint32_t)lane + kLanes) : 0;
             }
 #pragma unroll
+            for (int j = 0; j < K; j++) {
+                if ((uint32_t)lane < pin_n[j]) gs_lds[pin_pos[j] + lane] = v0[j];
+                if ((uint32_t)lane + kLanes < pin_n[j]) gs_lds[pin_pos[j] + kLanes + lane] = v1[j];
+            }
+#pragma unroll
+            for (int j = 0; j < K; j++) {
+                if (pin_n[j] > 2 * kLanes) {
+                    const int32_t *src = win.times + readlane64(c_off, (uint32_t)j * GT);
+                    for (uint32_t r = 2 * kLanes + lane; r < pin_n[j]; r += kLanes)
+                        gs_lds[pin_pos[j] + r] = ld_word(src, r);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else if (staged && bound > 0) {
+            // chunks scattered over the arena: copied one by one
             for (uint32_t c = 0; c < K * GT; c++) {
                 const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)c_tot, (int)c);
                 const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (int)c);
-                if ((uint32_t)lane < n) gs_lds[p + lane] = v[c];
-            }
-            if (__ballot(c_tot > (uint32_t)kLanes)) {
-                for (uint32_t c = 0; c < K * GT; c++) {
-                    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)c_tot, (int)c);
-                    const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (int)c);
-                    const uint64_t off = readlane64(c_off, c);
-                    for (uint32_t r = kLanes + lane; r < n; r += kLanes) gs_lds[p + r] = ld_word(win.times + off, r);
-                }
+                const int32_t *src = win.times + readlane64(c_off, c);
+                for (uint32_t r = lane; r < n; r += kLanes) gs_lds[p + r] = ld_word(src, r);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -689,23 +808,21 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             const uint32_t tile = tile0 + gb + u;
             const int32_t lc = (int32_t)(tile * kLanes) + lane;
             const bool active = lc < win.n_cycles;
+            // A lane past the window's last cycle has an empty list in every
+            // chunk (its lane end repeats the one before), so it walks nothing.
             uint32_t lo[K], hi[K], base[K];
-            const int32_t *chunk[K];
             uint32_t state0 = 0;
 #pragma unroll
             for (int j = 0; j < K; j++) {
                 const uint32_t c = (uint32_t)j * GT + u;
                 const uint64_t mask = readlane64(c_mask, c);
                 base[j] = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (int)c);
-                chunk[j] = win.times + readlane64(c_off, c);
-                const uint32_t e = ev[j][0];
-                const uint32_t l = wave_shr1(e);
-                lo[j] = active ? l : 0u;
-                hi[j] = active ? e : 0u;
+                hi[j] = ev[j][0] & 0xffffu;
+                lo[j] = wave_shr1(hi[j]);
                 state0 |= (uint32_t)((mask >> lane) & 1) << j;
             }
             const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
-            int32_t cnt, acc, z;
+            int32_t cnt, acc = 0, z = 0;
             if (staged) {
                 Cursor<K, WIRES, true> P;
 #pragma unroll
@@ -715,12 +832,15 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     P.end[j] = hi[j];
                 }
                 P.state = state0;
-                walk<K, WIRES, true, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
+                if constexpr (!WIRES)
+                    walk_lds<K, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, cnt);
+                else
+                    walk<K, WIRES, true, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
             } else {
                 Cursor<K, WIRES, false> P;
 #pragma unroll
                 for (int j = 0; j < K; j++) {
-                    P.chunk[j] = chunk[j];
+                    P.chunk[j] = win.times + readlane64(c_off, (uint32_t)j * GT + u);
                     P.idx[j] = lo[j];
                     P.end[j] = hi[j];
                 }
@@ -760,38 +880,58 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 h.mask = mask;
                 *glob(win.hdr + ci) = h;
             }
-            if (ok) {
-                int32_t *out = win.times + obase + (incl - ucnt);
-                const int32_t n = cnt < CAP ? cnt : CAP;
-                for (int32_t i = 0; i < n; i++) *glob(out + i) = gs_lds[out_lane + i * kLanes];
-                const uint64_t spill = __ballot(cnt > CAP);
-                if (spill) {
-                    // lanes whose list outgrew the staging walk again, from the
-                    // arena, writing to their place in the output chunk
-                    if (cnt > CAP) {
-                        Cursor<K, WIRES, false> P;
-#pragma unroll
-                        for (int j = 0; j < K; j++) {
-                            P.chunk[j] = chunk[j];
-                            P.idx[j] = lo[j];
-                            P.end[j] = hi[j];
-                        }
-                        P.state = state0;
-                        int32_t c2, a2, z2;
-                        walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, cnt, c2, a2, z2);
-                    }
-                    if (lane == 0)
-                        __hip_atomic_fetch_add(glob(win.flags + 2), (unsigned int)__popcll(spill), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+            // Copy the staged edges out and sum the lane's T1 terms from its
+            // final edge list: each edge toggles the value, and an edge at e
+            // to value v adds -min(e, T) if v = 1, +min(e, T) if v = 0.
+            int32_t *out = win.times + obase + (incl - ucnt);
+            const int32_t n = cnt < CAP ? cnt : CAP;
+            {
+                int v = y0;
+                int32_t s1 = 0;
+                for (int32_t i = 0; i < n; i++) {
+                    const int32_t e = gs_lds[out_lane + i * kLanes];
+                    if (ok) *glob(out + i) = e;
+                    v ^= 1;
+                    const int32_t ce = min(e, T);
+                    s1 += v ? -ce : ce;
                 }
+                if (!staged || WIRES) s1 = acc;      // those walks kept their own sum
+                acc = s1;
             }
+            const uint64_t spill = __ballot(cnt > CAP);
+            if (spill) {
+                // lanes whose list outgrew the staging walk again, from the
+                // arena, writing to their place in the output chunk (and
+                // returning the complete T1 sum)
+                if (cnt > CAP) {
+                    Cursor<K, WIRES, false> P;
+#pragma unroll
+                    for (int j = 0; j < K; j++) {
+                        P.chunk[j] = win.times + readlane64(c_off, (uint32_t)j * GT + u);
+                        P.idx[j] = lo[j];
+                        P.end[j] = hi[j];
+                    }
+                    P.state = state0;
+                    int32_t c2, z2;
+                    walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, ok ? cnt : 0, c2, acc,
+                                                  z2);
+                }
+                if (lane == 0 && ok)
+                    __hip_atomic_fetch_add(glob(win.flags + 2), (unsigned int)__popcll(spill), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            z = y0 ^ (cnt & 1);                      // every kept edge toggles the output
             tc_sum += total;
             nact_sum += (uint32_t)__popcll(__ballot(active));
             t1_lane += active ? z * T + acc : 0;
 #pragma unroll
             for (int j = 0; j < K; j++) {
-#pragma unroll
-                for (uint32_t k = 0; k + 1 < GT; k++) ev[j][k] = ev[j][k + 1];
+                if (GT == 4) {
+                    ev[j][0] = __builtin_amdgcn_alignbit(ev[j][GT / 2 - 1], ev[j][0], 16);
+                    ev[j][GT / 2 - 1] >>= 16;
+                } else {
+                    ev[j][0] >>= 16;
+                }
             }
         }
     }
@@ -818,8 +958,8 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int n, uin
 }
 
 // Wave w of a launch -> (segment, gate, group of tpw consecutive tiles).
-// LDS per wave: 64 words of delay table, CAP x 64 staged output words, then
-// the staged fanin words.
+// LDS per wave: 64 words of delay table, (CAP + 1) x 64 staged output words
+// (the last slot of each lane is a spare), then the staged fanin words.
 template <bool WIRES, int CAP, int KMAX, bool REMAP>
 __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ segs, int32_t n_segs, uint64_t n_waves,
                                                         uint32_t tpw)
@@ -842,9 +982,9 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const uint32_t tile0 = grp * tpw;
     const uint32_t ntl = min(tpw, ntile - tile0);
     const GateRec g = *kons(sg.gates + sg.gate_begin + gi);
-    const uint32_t lut_base = wib * (kLanes + CAP * kLanes + kStageWords);
+    const uint32_t lut_base = wib * (kLanes + (CAP + 1) * kLanes + kStageWords);
     const uint32_t out_base = lut_base + kLanes;
-    const uint32_t stage_base = out_base + CAP * kLanes;
+    const uint32_t stage_base = out_base + (CAP + 1) * kLanes;
     switch (g.k) {
     case 1: eval_gate<1, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
     case 2: eval_gate<2, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
@@ -861,7 +1001,7 @@ static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
                             hipStream_t s)
 {
     const uint64_t blocks = (n_waves + wpb - 1) / wpb;
-    const size_t lds = (size_t)wpb * ((size_t)cap * kLanes + kLanes + kStageWords) * sizeof(int32_t);
+    const size_t lds = (size_t)wpb * ((size_t)(cap + 1) * kLanes + kLanes + kStageWords) * sizeof(int32_t);
     const dim3 grid((unsigned)blocks), block(kLanes * wpb);
     switch (cap) {
     case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;

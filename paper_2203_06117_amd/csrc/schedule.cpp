@@ -371,7 +371,7 @@ int32_t default_window(gs_ctx *ctx, const Design *d)
 {
     int32_t W = ctx->opt.window_cycles;
     if (W <= 0) {
-        W = 4096;
+        W = 16384;
         while (W > kLanes && gs_header_bytes(d->N, W) * 3 > ctx->budget) W /= 2;
     }
     return W;
