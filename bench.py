@@ -80,7 +80,8 @@ def run_scale(args, torch, synth, GateSim):
     log(f"workload {w['name']}: {Gn} gates, {net['n_inputs']} inputs, {C} cycles, "
         f"{int(stim['toggle_ptr'][-1])} input toggles (generated in {time.time() - t_gen:.1f}s)")
     stream = torch.cuda.current_stream()
-    sim = GateSim(device=0, stream=stream, window_cycles=args.window, lds_cap=args.lds_cap,
+    window = args.window or min(C, 16384)
+    sim = GateSim(device=0, stream=stream, window_cycles=window, lds_cap=args.lds_cap,
                   waves_per_block=args.wpb, timing=not args.no_timing, tiles_per_wave=args.tpw)
     t_load = time.time()
     d, s = sim.load_work(w)
@@ -112,7 +113,7 @@ def run_scale(args, torch, synth, GateSim):
     gate_cycles = Gn * C * args.steps
     log(f"{args.steps} steps in {elapsed:.3f}s")
     tc = saif[0]
-    n_tiles_total = sum((min(args.window, C - c0) + 63) // 64 for c0 in range(0, C, args.window))
+    n_tiles_total = sum((min(window, C - c0) + 63) // 64 for c0 in range(0, C, window))
     alg_bytes_step = algorithmic_bytes(net, tc, C, n_tiles_total)
     launches = st["gate_eval_launches"]
     roofline = None
@@ -148,7 +149,7 @@ def run_scale(args, torch, synth, GateSim):
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
         "config": {"workload": "scale-1M", "gates": Gn, "inputs": net["n_inputs"], "levels": info.n_levels,
                    "cycles": C, "period_ps": stim["period"], "toggle_p": 0.15, "delays_ps": "5-80",
-                   "cond_frac": 0.10, "window_cycles": args.window, "lds_cap": args.lds_cap,
+                   "cond_frac": 0.10, "window_cycles": window, "lds_cap": args.lds_cap,
                    "waves_per_block": args.wpb, "tiles_per_wave": args.tpw},
         "kernel_gate_cycles_per_s": round(gate_cycles / (st["gate_eval_ms"] / 1e3), 1) if roofline else None,
         "transitions_per_gate_cycle": round(a_bar, 4),
@@ -224,7 +225,7 @@ def run_serve(args, torch, synth, G):
     works = synth.served_designs()
     log(f"served: {len(works)} resident netlists, {sum(w['netlist']['n_gates'] for w in works)} gates "
         f"(generated in {time.time() - t_gen:.1f}s)")
-    sim = G.GateSim(device=0)
+    sim = G.GateSim(device=0, tiles_per_wave=args.serve_tpw)
     ids = [sim.load_work(w, cells_loaded=i > 0) for i, w in enumerate(works)]
     resident = [(d, s, 0, 1000) for d, s in ids]
     t_r = time.perf_counter()
@@ -323,15 +324,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["all", "scale", "batch", "serve"], default="all")
     ap.add_argument("--cycles", type=int, default=10_000)
-    ap.add_argument("--window", type=int, default=1000)
+    ap.add_argument("--window", type=int, default=0, help="cycles per window (0 = the whole run, up to 16384)")
     ap.add_argument("--lds-cap", type=int, default=8)
-    ap.add_argument("--tpw", type=int, default=4)
+    ap.add_argument("--tpw", type=int, default=8)
     ap.add_argument("--wpb", type=int, default=4)
     ap.add_argument("--cpu-cycles", type=int, default=30, help="oracle sample: first N cycles (0 = skip)")
     ap.add_argument("--no-timing", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one elementwise kernel over this many MiB first (counter calibration)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-tpw", type=int, default=4, help="tiles per wave for the served requests")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -82,7 +82,7 @@ typedef struct {
     int32_t  waves_per_block; /* 1, 2, 4 or 8; 0 = 4 */
     int32_t  schedule;        /* GS_SCHED_LEVELS or GS_SCHED_GRAPH */
     int32_t  timing;          /* nonzero: time every gate-evaluation launch with HIP events (gs_get_stats) */
-    int32_t  tiles_per_wave;  /* consecutive 64-cycle tiles of one gate evaluated by one wave; 0 = 4 */
+    int32_t  tiles_per_wave;  /* consecutive 64-cycle tiles of one gate evaluated by one wave; 0 = 8 */
     int32_t  autotune;        /* nonzero: gs_simulate_batch picks lds_cap, waves_per_block and tiles_per_wave by
                                  timing candidates on its largest job (once per batch shape) */
     int32_t  reserved[5];

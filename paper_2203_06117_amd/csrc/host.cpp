@@ -207,7 +207,7 @@ extern "C" void gs_default_options(gs_options *o)
     std::memset(o, 0, sizeof(*o));
     o->lds_cap = 8;
     o->waves_per_block = 4;
-    o->tiles_per_wave = 4;
+    o->tiles_per_wave = 8;
     o->schedule = GS_SCHED_LEVELS;
 }
 
@@ -238,7 +238,7 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
     else gs_default_options(&o);
     if (o.lds_cap == 0) o.lds_cap = 8;
     if (o.waves_per_block == 0) o.waves_per_block = 4;
-    if (o.tiles_per_wave == 0) o.tiles_per_wave = 4;
+    if (o.tiles_per_wave == 0) o.tiles_per_wave = 8;
     if (o.tiles_per_wave < 1 || o.tiles_per_wave > 64) return gs_fail(nullptr, GS_E_INVALID, "tiles_per_wave must be 1..64");
     if (o.lds_cap != 4 && o.lds_cap != 8 && o.lds_cap != 16 && o.lds_cap != 32)
         return gs_fail(nullptr, GS_E_INVALID, "lds_cap must be 4, 8, 16 or 32");

@@ -179,20 +179,29 @@ __global__ void level_init_kernel(int32_t *level, int32_t n_inputs, int32_t n_ne
 __global__ void level_step_kernel(const int64_t *__restrict__ fanin_ptr, const int32_t *__restrict__ fanin_net,
                                   int32_t *level, int32_t n_inputs, int32_t n_gates, unsigned int *counters)
 {
-    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_gates) return;
-    if (level[n_inputs + g] >= 0) return;
-    int32_t mx = 0;
-    for (int64_t s = fanin_ptr[g]; s < fanin_ptr[g + 1]; s++) {
-        int32_t l = __hip_atomic_load(&level[fanin_net[s]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (l < 0) {
-            atomicAdd(&counters[1], 1u);
-            return;
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    bool placed = false, blocked = false;
+    if (g < n_gates && level[n_inputs + g] < 0) {
+        int32_t mx = 0;
+        for (int64_t s = fanin_ptr[g]; s < fanin_ptr[g + 1]; s++) {
+            const int32_t l = __hip_atomic_load(&level[fanin_net[s]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (l < 0) {
+                blocked = true;
+                break;
+            }
+            mx = l > mx ? l : mx;
         }
-        mx = l > mx ? l : mx;
+        if (!blocked) {
+            __hip_atomic_store(&level[n_inputs + g], mx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            placed = true;
+        }
     }
-    __hip_atomic_store(&level[n_inputs + g], mx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicAdd(&counters[0], 1u);
+    // one update of each counter per wave
+    const uint64_t bp = __ballot(placed), bb = __ballot(blocked);
+    if ((threadIdx.x & (kLanes - 1)) == 0) {
+        if (bp) atomicAdd(&counters[0], (unsigned int)__popcll(bp));
+        if (bb) atomicAdd(&counters[1], (unsigned int)__popcll(bb));
+    }
 }
 
 // count_only: cursor[level] += 1 per gate (histogram).  Otherwise cursor
@@ -419,6 +428,17 @@ constexpr uint32_t kStageWords = 512;
 __device__ __forceinline__ int32_t ld_word(const int32_t *chunk, uint32_t idx)
 {
     return *(const GAS int32_t *)((const GAS char *)glob(chunk) + (uint64_t)(idx << 2));
+}
+
+// base[idx] = v for a wave-uniform base (scalar base + 32-bit vector offset)
+__device__ __forceinline__ void st_word(int32_t *base, uint32_t idx, int32_t v)
+{
+    *(GAS int32_t *)((GAS char *)glob(base) + (uint64_t)(idx << 2)) = v;
+}
+
+__device__ __forceinline__ void st_u16(uint16_t *base, uint32_t idx, uint16_t v)
+{
+    *(GAS uint16_t *)((GAS char *)glob(base) + (uint64_t)(idx << 1)) = v;
 }
 
 // base[idx] for a wave-uniform base (scalar base + 32-bit vector offset)
@@ -803,7 +823,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        uint64_t used = 0;
+        uint32_t used = 0;                                      // words of the reservation handed out
         for (uint32_t u = 0; u < ng; u++) {
             const uint32_t tile = tile0 + gb + u;
             const int32_t lc = (int32_t)(tile * kLanes) + lane;
@@ -871,9 +891,10 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = false;
             }
+            ok = uniform(ok ? 1u : 0u) != 0;
             const uint64_t obase = wbase + used;
             if (ok) used += total;
-            *glob(win.ends + ci * kLanes + lane) = ok ? (uint16_t)incl : (uint16_t)0;
+            st_u16(win.ends + ci * kLanes, (uint32_t)lane, ok ? (uint16_t)incl : (uint16_t)0);
             if (lane == 0) {
                 ChunkHdr h;
                 h.off = ok ? obase : 0;
@@ -883,14 +904,16 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             // Copy the staged edges out and sum the lane's T1 terms from its
             // final edge list: each edge toggles the value, and an edge at e
             // to value v adds -min(e, T) if v = 1, +min(e, T) if v = 0.
-            int32_t *out = win.times + obase + (incl - ucnt);
+            int32_t *out_chunk = win.times + obase;
+            const uint32_t first = incl - ucnt;
+            int32_t *out = out_chunk + first;
             const int32_t n = cnt < CAP ? cnt : CAP;
             {
                 int v = y0;
                 int32_t s1 = 0;
                 for (int32_t i = 0; i < n; i++) {
                     const int32_t e = gs_lds[out_lane + i * kLanes];
-                    if (ok) *glob(out + i) = e;
+                    if (ok) st_word(out_chunk, first + (uint32_t)i, e);
                     v ^= 1;
                     const int32_t ce = min(e, T);
                     s1 += v ? -ce : ce;
@@ -1042,12 +1065,16 @@ __global__ void cone_mark_kernel(const GateRec *__restrict__ gates, const PinRec
                                  uint32_t n_gates, uint8_t *mark, unsigned int *count)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_gates) return;
-    const GateRec g = gates[gate_begin + i];
-    uint8_t m = mark[g.out];
-    for (uint32_t j = 0; j < g.k; j++) m |= mark[pins[g.pin0 + j].net];
-    mark[g.out] = m;
-    if (m) atomicAdd(count, 1u);
+    bool in_cone = false;
+    if (i < n_gates) {
+        const GateRec g = gates[gate_begin + i];
+        uint8_t m = mark[g.out];
+        for (uint32_t j = 0; j < g.k; j++) m |= mark[pins[g.pin0 + j].net];
+        mark[g.out] = m;
+        in_cone = m != 0;
+    }
+    const uint64_t b = __ballot(in_cone);                  // one counter update per wave
+    if ((threadIdx.x & (kLanes - 1)) == 0 && b) atomicAdd(count, (unsigned int)__popcll(b));
 }
 
 hipError_t launch_cone_mark(const GateRec *gates, const PinRec *pins, uint32_t gate_begin, uint32_t n_gates,
@@ -1082,11 +1109,34 @@ __global__ void cone_place_kernel(const GateRec *__restrict__ gates, const PinRe
                                   uint32_t stride, int32_t *slot, uint32_t n_cone)
 {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_gates) return;
-    GateRec g = gates[p];
-    if (!mark[g.out]) return;
-    const int32_t l = level[g.out];
-    const uint32_t pos = off[l] + atomicAdd(&cur[l], 1u);
+    const int lane = threadIdx.x & (kLanes - 1);
+    GateRec g = {};
+    bool in_cone = false;
+    int32_t l = 0;
+    if (p < n_gates) {
+        g = gates[p];
+        in_cone = mark[g.out] != 0;
+        if (in_cone) l = level[g.out];
+    }
+    // Gates are in level order, so the cone gates of a wave nearly always
+    // share one level: they then take their places with one atomic.
+    const uint64_t act = __ballot(in_cone);
+    if (!act) return;
+    const int first = __builtin_ctzll(act);
+    const int32_t l0 = __builtin_amdgcn_readlane(l, first);
+    const uint64_t same = __ballot(in_cone && l == l0);
+    uint32_t pos = 0;
+    if (same == act) {
+        uint32_t base = 0;
+        if (lane == first) base = atomicAdd(&cur[l0], (unsigned int)__popcll(act));
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, first);
+        const uint32_t below = (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+        pos = off[l] + base + below;
+    } else if (in_cone) {
+        pos = off[l] + atomicAdd(&cur[l], 1u);
+    }
+    if (!in_cone) return;
     if (pos >= off[l + 1] || pos >= n_cone) return;      // counts and marks disagree: never write outside the cone
     const uint32_t pin0 = g.pin0;
     g.pin0 = pos * stride;

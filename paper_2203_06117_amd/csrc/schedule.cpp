@@ -424,7 +424,7 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
 // keeps the fastest in the context.
 static gs_status autotune_impl(gs_ctx *ctx, const std::vector<Piece> &trial, Tuning *best_out, double *best_ms)
 {
-    static const Tuning cands[] = {{8, 4, 4}, {8, 4, 2}, {8, 4, 8}, {8, 2, 4}, {16, 4, 4}, {8, 8, 4}, {16, 2, 8}, {8, 4, 1}};
+    static const Tuning cands[] = {{8, 4, 8}, {8, 4, 4}, {8, 2, 8}, {8, 4, 16}, {16, 4, 8}, {8, 8, 8}, {8, 4, 2}, {4, 4, 8}};
     double best = 1e30;
     Tuning bt = current_tuning(ctx);
     const int saved_sched = ctx->opt.schedule;
