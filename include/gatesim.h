@@ -197,7 +197,8 @@ typedef struct {
     int64_t  spilled_lanes;     /* (net, cycle) lists longer than the on-chip staging cap */
     int64_t  arena_words;       /* 32-bit transition slots used by the last window */
     int64_t  graph_launches;    /* rounds replayed from a captured HIP graph */
-    int64_t  reserved[5];
+    int64_t  unstaged_groups;   /* (gate, tile group) waves whose fanin words exceeded the on-chip stage */
+    int64_t  reserved[4];
 } gs_stats;
 
 gs_status gs_get_stats(gs_ctx *ctx, gs_stats *st, int32_t reset);

@@ -49,7 +49,8 @@ struct WinView {
     uint16_t *ends;
     int32_t *times;
     unsigned long long *bump;      // one counter per stripe, kBumpStride apart: words handed out in the stripe
-    unsigned int *flags;           // [0] arena full, [1] chunk over 65535, [2] spilled lanes, [3] bound violated
+    unsigned int *flags;           // [0] arena full, [1] chunk over 65535, [2] spilled lanes, [3] bound violated,
+                                   // [4] tile groups walked from the arena (too many words to stage)
     uint64_t slice_words;          // arena words owned by each stripe
     uint64_t arena_off;            // first word of this window's arena, counted from `times`
     int32_t n_tiles;

@@ -772,6 +772,8 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         uint64_t wbase = 0;
         bool wok = true, placed = false;
         const bool staged = bound <= kStageWords;
+        if (!staged && lane == 0)                               // counted for the statistics
+            __hip_atomic_fetch_add(glob(win.flags + 4), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // A producing wave places the chunks of its tile group one after
         // another, so a pin's chunks in this group are usually one
         // contiguous range of the arena, and the stage keeps them in the same

@@ -256,6 +256,7 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     for (uint32_t i = 0; i <= v0.stripe_mask; i++) used += std::min<uint64_t>(hb[(size_t)i * kBumpStride], v0.slice_words);
     ctx->stats.arena_words = (int64_t)used;
     ctx->stats.spilled_lanes += f32[2];
+    ctx->stats.unstaged_groups += f32[4];
     if (f32[3]) return gs_fail(ctx, GS_E_DEVICE, "internal error: an output chunk exceeded its fanin bound");
     if (f32[1]) return gs_fail(ctx, GS_E_CAPACITY, "more than %u transitions in one (net, 64-cycle tile)", kMaxChunk);
     if (f32[0]) {

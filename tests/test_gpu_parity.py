@@ -126,7 +126,8 @@ def test_tiny_config_waveforms(G):
 
 @pytest.mark.parametrize("opt", [dict(window_cycles=64), dict(window_cycles=37), dict(window_cycles=100),
                                  dict(lds_cap=4), dict(lds_cap=32, waves_per_block=1),
-                                 dict(waves_per_block=8, lds_cap=8), dict(window_cycles=300, hbm_budget=1_900_000)])
+                                 dict(waves_per_block=8, lds_cap=8), dict(window_cycles=300, hbm_budget=1_900_000),
+                                 dict(tiles_per_wave=1), dict(tiles_per_wave=3), dict(tiles_per_wave=16, lds_cap=16)])
 def test_invariance(G, opt):
     """Same SAIF for every window size, staging cap, block shape and for a
     budget so small that windows shrink and the transition arena refills."""
@@ -138,6 +139,19 @@ def test_invariance(G, opt):
         assert got[4]["spilled_lanes"] > 0
     if opt.get("hbm_budget"):
         assert got[4]["window_retries"] > 0
+
+
+def test_dense_activity(G):
+    """Inputs with about six toggles per cycle: tile groups carry more fanin
+    words than the on-chip stage holds, so waves walk the arena directly, and
+    output lists outgrow the LDS staging; both paths must match the oracle."""
+    w = synth.small_random(77, 600, 16, 12, 200, 2000, 0.9, 2, 60, cond_frac=0.2, extra=6, extra_p=0.9)
+    for opt in (dict(), dict(tiles_per_wave=2, lds_cap=4)):
+        say("dense", opt)
+        got = gpu_saif(G, w, **opt)
+        assert_same(w, got, oracle.simulate(w), f"dense {opt}")
+        assert got[4]["unstaged_groups"] > 0
+        assert got[4]["spilled_lanes"] > 0
 
 
 def test_cycle_subranges(G):
