@@ -63,7 +63,7 @@ typedef int32_t gs_status;
 #define GS_E_DEVICE    -4   /* a HIP runtime call failed or no GPU is present */
 #define GS_E_STATE     -5   /* call out of order (e.g. simulate before arcs) */
 #define GS_E_BUSY      -6   /* serving admission queue is full */
-#define GS_E_CAPACITY  -7   /* more than 65535 transitions in one net's 64-cycle tile */
+#define GS_E_CAPACITY  -7   /* more than 32767 transitions in one net's 64-cycle tile */
 
 typedef struct gs_ctx gs_ctx;
 

@@ -762,7 +762,7 @@ extern "C" gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim,
     HIPCHK(hipMemcpyAsync(&h, ctx->win.hdr + ci, sizeof(h), hipMemcpyDeviceToHost, hs));
     HIPCHK(hipMemcpyAsync(e, ctx->win.ends + ci * kLanes, sizeof(e), hipMemcpyDeviceToHost, hs));
     HIPCHK(hipStreamSynchronize(hs));
-    const uint32_t lo = lane ? e[lane - 1] : 0, hi = e[lane];
+    const uint32_t lo = lane ? e[lane - 1] & kEndCount : 0, hi = e[lane] & kEndCount;
     if (init) *init = (int32_t)((h.mask >> lane) & 1);
     if (n) *n = (int32_t)(hi - lo);
     const uint32_t m = std::min<uint32_t>(hi - lo, cap > 0 ? (uint32_t)cap : 0u);

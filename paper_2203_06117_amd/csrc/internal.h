@@ -9,7 +9,12 @@ namespace gs {
 
 constexpr int kLanes = 64;                  // wavefront size on CDNA; one lane per cycle of a tile
 constexpr int32_t kInf = 0x7fffffff;        // end-of-waveform time (Algorithm 1's EOW)
-constexpr uint32_t kMaxChunk = 65535;       // transitions per (net, 64-cycle tile): 16-bit lane ends
+// A lane end is 16 bits: the inclusive transition count of the chunk up to
+// that lane (15 bits) and, in bit 15, the net's value at the start of the
+// lane's cycle.
+constexpr uint32_t kMaxChunk = 32767;       // transitions per (net, 64-cycle tile)
+constexpr uint32_t kEndCount = 0x7fffu;
+constexpr uint32_t kEndInitShift = 15;
 
 // One gate in level order (the level partition of Section 3), 32 bytes.
 struct GateRec {
@@ -49,7 +54,7 @@ struct WinView {
     uint16_t *ends;
     int32_t *times;
     unsigned long long *bump;      // one counter per stripe, kBumpStride apart: words handed out in the stripe
-    unsigned int *flags;           // [0] arena full, [1] chunk over 65535, [2] spilled lanes, [3] bound violated,
+    unsigned int *flags;           // [0] arena full, [1] chunk over kMaxChunk, [2] spilled lanes, [3] bound violated,
                                    // [4] tile groups walked from the arena (too many words to stage)
     uint64_t slice_words;          // arena words owned by each stripe
     uint64_t arena_off;            // first word of this window's arena, counted from `times`

@@ -40,12 +40,6 @@ __device__ __forceinline__ const CAS T *kons(const T *p)
     return (const CAS T *)p;
 }
 
-// Transitions in chunk ci (the inclusive lane end of its last lane).
-__device__ __forceinline__ uint32_t chunk_total(const uint16_t *ends, uint64_t ci)
-{
-    const uint32_t w = *kons((const uint32_t *)(ends + ci * kLanes + kLanes - 2));
-    return w >> 16;
-}
 
 
 // --------------------------------------------------------------------------
@@ -357,7 +351,8 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
             okc = false;
         }
         const uint64_t ci = (uint64_t)i * ntile + tile;
-        *glob(win.ends + ci * kLanes + lane) = okc ? (uint16_t)incl[u] : (uint16_t)0;
+        const uint32_t init = (uint32_t)((mask[u] >> lane) & 1);
+        *glob(win.ends + ci * kLanes + lane) = (uint16_t)((okc ? incl[u] : 0u) | (init << kEndInitShift));
         if (lane == 0) {
             ChunkHdr h;
             h.off = okc ? base : 0;
@@ -743,8 +738,8 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         const bool cval = cj < (uint32_t)K && cu < ng;
         const uint64_t cci = (uint64_t)crow * ntile + tile0 + gb + min(cu, ng - 1);
         const ChunkHdr ch = *glob(chsrc + cci);
-        const uint32_t c_tot = cval ? (uint32_t)*glob(cesrc + cci * kLanes + kLanes - 1) : 0u;
-        const uint64_t c_off = ch.off, c_mask = ch.mask;
+        const uint32_t c_tot = cval ? (uint32_t)*glob(cesrc + cci * kLanes + kLanes - 1) & kEndCount : 0u;
+        const uint64_t c_off = ch.off;
         // lane ends of pin j in tiles u and u+1 of the group share one word
         uint32_t ev[K][GT / 2];
 #pragma unroll
@@ -762,7 +757,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         // appends at most one edge per event), so the fanin totals bound it.
         const uint32_t c_incl = wave_incl_scan(c_tot);
         const uint32_t bound = (uint32_t)lane63(c_incl);
-        const uint32_t c_pos = stage_base + c_incl - c_tot;     // chunk's first word in the LDS stage
+        const uint32_t c_pos = stage_base + wave_shr1(c_incl);  // chunk's first word in the LDS stage
         // (the returned offset is first needed after the walk of the first tile)
         const uint32_t stripe = (blockIdx.x + sg.salt) & win.stripe_mask;
         uint64_t bres = 0;
@@ -837,11 +832,10 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
 #pragma unroll
             for (int j = 0; j < K; j++) {
                 const uint32_t c = (uint32_t)j * GT + u;
-                const uint64_t mask = readlane64(c_mask, c);
                 base[j] = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, (int)c);
-                hi[j] = ev[j][0] & 0xffffu;
+                hi[j] = ev[j][0] & kEndCount;
                 lo[j] = wave_shr1(hi[j]);
-                state0 |= (uint32_t)((mask >> lane) & 1) << j;
+                state0 |= ((ev[j][0] >> kEndInitShift) & 1u) << j;
             }
             const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
             int32_t cnt, acc = 0, z = 0;
@@ -896,7 +890,8 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             ok = uniform(ok ? 1u : 0u) != 0;
             const uint64_t obase = wbase + used;
             if (ok) used += total;
-            st_u16(win.ends + ci * kLanes, (uint32_t)lane, ok ? (uint16_t)incl : (uint16_t)0);
+            st_u16(win.ends + ci * kLanes, (uint32_t)lane,
+                   (uint16_t)((ok ? incl : 0u) | ((active && y0) ? 1u << kEndInitShift : 0u)));
             if (lane == 0) {
                 ChunkHdr h;
                 h.off = ok ? obase : 0;
@@ -907,7 +902,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             // final edge list: each edge toggles the value, and an edge at e
             // to value v adds -min(e, T) if v = 1, +min(e, T) if v = 0.
             int32_t *out_chunk = win.times + obase;
-            const uint32_t first = incl - ucnt;
+            const uint32_t first = wave_shr1(incl);            // exclusive prefix: the lane's first slot
             int32_t *out = out_chunk + first;
             const int32_t n = cnt < CAP ? cnt : CAP;
             {

@@ -656,7 +656,7 @@ void serve_loop(gs_ctx *ctx, ServeState *S)
             } else if (fl[3]) {
                 finish(S, *q, GS_E_DEVICE, "internal error: an output chunk exceeded its fanin bound");
             } else if (fl[1]) {
-                finish(S, *q, GS_E_CAPACITY, "more than 65535 transitions in one (net, 64-cycle tile)");
+                finish(S, *q, GS_E_CAPACITY, "more than 32767 transitions in one (net, 64-cycle tile)");
             } else if (fl[0]) {
                 // the arena filled up: run the request again with twice the arena
                 S->pool.release(q->region);
@@ -806,7 +806,7 @@ extern "C" gs_status gs_serve_start(gs_ctx *ctx, int32_t n_resident, const int32
             if (hipMemcpyAsync(fl, q.flags, sizeof(fl), hipMemcpyDeviceToHost, S->st) != hipSuccess ||
                 hipStreamSynchronize(S->st) != hipSuccess) { st = GS_E_DEVICE; err = "resident window"; break; }
             if (fl[3]) { st = GS_E_DEVICE; err = "internal error: an output chunk exceeded its fanin bound"; break; }
-            if (fl[1]) { st = GS_E_CAPACITY; err = "resident window exceeds 65535 transitions per chunk"; break; }
+            if (fl[1]) { st = GS_E_CAPACITY; err = "resident window exceeds 32767 transitions per chunk"; break; }
             if (!fl[0]) break;
             S->pool.release(q.region);
             q.region = Region();
