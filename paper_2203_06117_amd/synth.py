@@ -78,9 +78,26 @@ CELL_TRUTH = np.array([0x1, 0x2, 0x7, 0x1, 0x80, 0x6, 0x07, 0xCA], dtype=np.uint
 INV, BUF, NAND2, NOR2, AND3, XOR2, AOI21, MUX2 = range(8)
 
 
+def _truth(k: int, f) -> int:
+    """Truth bits of a k-pin cell: bit s is f(pin values), pin j = bit j of s."""
+    return sum(1 << s for s in range(1 << k) if f(*[(s >> j) & 1 for j in range(k)]))
+
+
+# The base library plus cells of four to six pins (same indices for the base
+# cells), for netlists that exercise wide gates.
+WIDE_NAMES = CELL_NAMES + ["AND4", "OAI22", "AOI221", "AOI222"]
+WIDE_PINS = np.append(CELL_PINS, np.array([4, 4, 5, 6], dtype=np.uint8)).astype(np.uint8)
+WIDE_TRUTH = np.append(CELL_TRUTH, np.array([
+    _truth(4, lambda a, b, c, d: a & b & c & d),
+    _truth(4, lambda a, b, c, d: 1 - ((a | b) & (c | d))),
+    _truth(5, lambda a, b, c, d, e: 1 - ((a & b) | (c & d) | e)),
+    _truth(6, lambda a, b, c, d, e, f: 1 - ((a & b) | (c & d) | (e & f))),
+], dtype=np.uint64)).astype(np.uint64)
+
+
 def make_netlist(seed: int, n_gates: int, n_inputs: int, n_levels: int,
                  cell_probs=None, fanout_mean: float = 2.5,
-                 arith_frac: float = 0.0, shuffle: bool = True) -> dict:
+                 arith_frac: float = 0.0, shuffle: bool = True, wide: bool = False) -> dict:
     """Random levelized DAG.
 
     Gates are split evenly over ``n_levels`` levels.  Pin 0 of a level-l gate
@@ -92,7 +109,8 @@ def make_netlist(seed: int, n_gates: int, n_inputs: int, n_levels: int,
     of the gates is instead laid out as ripple-carry adder slices (XOR2 sum,
     MUX2 carry select, AND3/AOI21 side logic) chained across consecutive
     levels, giving deep reconvergent XOR/MUX cones.  Gate ids are a random
-    permutation of the level order unless ``shuffle`` is False.
+    permutation of the level order unless ``shuffle`` is False.  ``wide``
+    draws cells from the library with four- to six-pin cells as well.
     """
     G, I, L = int(n_gates), int(n_inputs), int(n_levels)
     if G < L or L < 1 or I < 3:
@@ -107,14 +125,16 @@ def make_netlist(seed: int, n_gates: int, n_inputs: int, n_levels: int,
     lvl_start = np.concatenate([[0], np.cumsum(per)])           # level-order gate index range per level
     level_of_q = np.repeat(np.arange(1, L + 1, dtype=np.int64), per)
 
+    lib_pins, lib_truth = (WIDE_PINS, WIDE_TRUTH) if wide else (CELL_PINS, CELL_TRUTH)
+    n_cells = len(lib_pins)
     q = np.arange(G, dtype=np.int64)
     if cell_probs is None:
-        cell = s_cell.below(q, 8).astype(np.int32)
+        cell = s_cell.below(q, n_cells).astype(np.int32)
     else:
         cp = np.cumsum(np.asarray(cell_probs, dtype=np.float64))
         cp /= cp[-1]
         cell = np.searchsorted(cp, s_cell.unit(q), side="right").astype(np.int32)
-        cell = np.minimum(cell, 7)
+        cell = np.minimum(cell, n_cells - 1)
 
     # arithmetic-like chains: overwrite the cell of a fraction of gates so
     # that chains of (XOR2 sum, MUX2 carry) pairs walk up consecutive levels
@@ -125,7 +145,7 @@ def make_netlist(seed: int, n_gates: int, n_inputs: int, n_levels: int,
         pat = np.array([XOR2, MUX2, XOR2, MUX2, AND3, XOR2, AOI21, MUX2], dtype=np.int32)
         cell = np.where(arith, pat[(q % 8)], cell)
 
-    k = CELL_PINS[cell].astype(np.int64)
+    k = lib_pins[cell].astype(np.int64)
 
     n_nets = I + G
     m = np.arange(n_nets, dtype=np.int64)
@@ -192,8 +212,8 @@ def make_netlist(seed: int, n_gates: int, n_inputs: int, n_levels: int,
         "fanin_ptr": fanin_ptr,
         "fanin_net": fanin_net,
         "level_hint": level_of_q[order].astype(np.int32),
-        "cell_pins": CELL_PINS.copy(),
-        "cell_truth": CELL_TRUTH.copy(),
+        "cell_pins": lib_pins.copy(),
+        "cell_truth": lib_truth.copy(),
     }
 
 
@@ -351,9 +371,9 @@ def glitchy(seed: int = 3, n_gates: int = 8_000_000, n_inputs: int = 150_000,
 def small_random(seed: int, n_gates: int, n_inputs: int, n_levels: int, n_cycles: int,
                  period: int, p: float, dlo: int, dhi: int, cond_frac: float = 0.0,
                  wire: tuple | None = None, extra: int = 0, extra_p: float = 0.0,
-                 skew: int = 50) -> dict:
+                 skew: int = 50, wide: bool = False) -> dict:
     """Parametric small workload used by parity and property tests."""
-    net = make_netlist(seed, n_gates, n_inputs, n_levels)
+    net = make_netlist(seed, n_gates, n_inputs, n_levels, wide=wide)
     wires = make_wires(seed, net, wire[0], wire[1]) if wire else None
     return {"name": f"rand-{seed}", "netlist": net,
             "arcs": make_arcs(seed, net, dlo, dhi, cond_frac), "wires": wires,

@@ -7,7 +7,7 @@ import numpy as np
 
 from paper_2203_06117_amd import synth
 
-CELL = {name: i for i, name in enumerate(synth.CELL_NAMES)}
+CELL = {name: i for i, name in enumerate(synth.WIDE_NAMES)}
 
 
 def work(n_inputs, gates, delays, toggles, init, period=1000, n_cycles=1, wires=None):
@@ -39,8 +39,8 @@ def work(n_inputs, gates, delays, toggles, init, period=1000, n_cycles=1, wires=
         w = {"rise": np.array([x[0] for x in wires], dtype=np.int32),
              "fall": np.array([x[1] for x in wires], dtype=np.int32)}
     net = {"n_inputs": n_inputs, "n_gates": len(gates), "cell_of_gate": cog,
-           "fanin_ptr": fp, "fanin_net": fn, "cell_pins": synth.CELL_PINS.copy(),
-           "cell_truth": synth.CELL_TRUTH.copy()}
+           "fanin_ptr": fp, "fanin_net": fn, "cell_pins": synth.WIDE_PINS.copy(),
+           "cell_truth": synth.WIDE_TRUTH.copy()}
     stim = {"period": period, "n_cycles": n_cycles, "init": np.array(init, dtype=np.uint8),
             "toggle_ptr": tp, "toggle_ps": ts}
     return {"name": "handmade", "netlist": net, "arcs": arcs, "wires": w, "stimulus": stim}

@@ -31,8 +31,9 @@ def same(got, ref, tag):
             raise AssertionError(f"{tag}: {name} differs on {len(bad)} nets, first {bad[:6]}")
 
 
-def uneven_jobs(n, seed0=400, gmax=3000):
-    """Uneven instances shaped like the batched workload, scaled to oracle size."""
+def uneven_jobs(n, seed0=400, gmax=3000, wide_every=0):
+    """Uneven instances shaped like the batched workload, scaled to oracle size
+    (every ``wide_every``-th one drawing four- to six-pin cells as well)."""
     works = []
     rng = np.random.default_rng(seed0)
     for i in range(n):
@@ -41,7 +42,10 @@ def uneven_jobs(n, seed0=400, gmax=3000):
         levels = max(2, int(round(6 + 20 * np.log(g / 200) / np.log(gmax / 200))))
         cycles = int(np.exp(rng.uniform(np.log(20), np.log(300))))
         p = float(rng.uniform(0.05, 0.3))
-        works.append(synth.small_random(seed0 + i, g, inputs, min(levels, g), cycles, 800, p, 5, 80, cond_frac=0.1))
+        wide = wide_every > 0 and i % wide_every == 1
+        inputs = max(inputs, 8) if wide else inputs
+        works.append(synth.small_random(seed0 + i, g, inputs, min(levels, g), cycles, 800, p, 5, 80, cond_frac=0.1,
+                                        wide=wide))
     return works
 
 
@@ -66,11 +70,12 @@ def test_graph_replays(G):
 
 
 def test_batch_uneven_instances(G):
-    works = uneven_jobs(10)
+    works = uneven_jobs(10, wide_every=3)
     with G.GateSim() as sim:
+        sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)         # a superset of every instance's library
         ids = []
-        for i, w in enumerate(works):
-            ids.append(sim.load_work(w, cells_loaded=i > 0))
+        for w in works:
+            ids.append(sim.load_work(w, cells_loaded=True))
         jobs = [(d, s, 0, w["stimulus"]["n_cycles"]) for (d, s), w in zip(ids, works)]
         say("batch", [w["netlist"]["n_gates"] for w in works])
         sim.simulate_batch(jobs)

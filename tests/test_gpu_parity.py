@@ -154,6 +154,25 @@ def test_dense_activity(G):
         assert got[4]["spilled_lanes"] > 0
 
 
+@pytest.mark.parametrize("opt", [dict(), dict(tiles_per_wave=3), dict(lds_cap=4, waves_per_block=2)])
+def test_wide_cells(G, opt):
+    """Cells of four to six pins (no delay lookup table; arc delays chosen per
+    event, two tiles per staging group) mixed with the base cells, with
+    conditional arcs and glitchy inputs, with and without wire delays."""
+    for wire in (None, (1, 6)):
+        w = synth.small_random(91, 1500, 40, 20, 200, 600, 0.3, 2, 60, cond_frac=0.2, extra=2, extra_p=0.3,
+                               wide=True, wire=wire)
+        say("wide", opt, wire)
+        rng = np.random.default_rng(5)
+        N = 40 + 1500
+        probes = [(int(n), int(c)) for n, c in zip(rng.integers(40, N, 200), rng.integers(0, 200, 200))]
+        ref = oracle.simulate(w, probes=probes)
+        got = gpu_saif(G, w, probes=probes, **opt)
+        assert_same(w, got, ref, f"wide {opt} {wire}")
+        for (n, c), g_, o_ in zip(probes, got[3], ref["probes"]):
+            assert g_ == o_, (n, c)
+
+
 def test_cycle_subranges(G):
     """Accumulating disjoint sub-ranges equals the whole range; a range can
     start and end anywhere (ragged tiles on both sides)."""

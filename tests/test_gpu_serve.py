@@ -59,10 +59,12 @@ def random_edits(rng, w, n):
 
 @pytest.fixture(scope="module")
 def served(G):
-    works = [synth.small_random(600 + i, g, max(4, g // 50), lv, 400, 800, 0.2, 5, 80, cond_frac=0.1)
+    # the third design also has four- to six-pin cells
+    works = [synth.small_random(600 + i, g, max(8, g // 50), lv, 400, 800, 0.2, 5, 80, cond_frac=0.1, wide=i == 2)
              for i, (g, lv) in enumerate(((3000, 30), (1200, 20), (600, 12)))]
     sim = G.GateSim()
-    ids = [sim.load_work(w, cells_loaded=i > 0) for i, w in enumerate(works)]
+    sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)
+    ids = [sim.load_work(w, cells_loaded=True) for w in works]
     resident = [(d, s, 100, 150) for d, s in ids]
     sim.serve_start(resident, max_queue=1000)
     yield sim, works, ids, resident

@@ -21,24 +21,24 @@ from oracle import brute
 from paper_2203_06117_amd import synth
 
 
-def _tiny(seed, wires, cond, zero):
+def _tiny(seed, wires, cond, zero, wide=False):
     rng = np.random.default_rng(seed)
     G = int(rng.integers(1, 11))
-    I = int(rng.integers(3, 5))
+    I = int(rng.integers(3, 5)) + (3 if wide else 0)
     L = int(rng.integers(1, min(G, 4) + 1))
     T = int(rng.integers(25, 45))
     dlo, dhi = (0, 0) if zero else (1, int(rng.integers(1, 9)))
     w = synth.small_random(seed, G, I, L, 3, T, 0.5, dlo, dhi, cond_frac=0.5 if cond else 0.0,
                            wire=None if (zero or not wires) else (1, int(rng.integers(1, 7))),
-                           extra=2, extra_p=0.4, skew=T - 1)
+                           extra=2, extra_p=0.4, skew=T - 1, wide=wide)
     return w
 
 
-@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero"])
+@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "wide", "wide+wires+cond"])
 def test_oracle_matches_brute(mode):
     n_ok = 0
     for seed in range(1000, 1120):
-        w = _tiny(seed, "wires" in mode, "cond" in mode, mode == "zero")
+        w = _tiny(seed, "wires" in mode, "cond" in mode, mode == "zero", wide="wide" in mode)
         tc, t0, t1, waves = brute.simulate(w)
         N = len(tc)
         C = w["stimulus"]["n_cycles"]

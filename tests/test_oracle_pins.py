@@ -26,6 +26,10 @@ TEXTBOOK = {
     "XOR2": lambda a, b: a ^ b,
     "AOI21": lambda a1, a2, b: 1 - ((a1 & a2) | b),
     "MUX2": lambda i0, i1, s: i1 if s else i0,
+    "AND4": lambda a, b, c, d: a & b & c & d,
+    "OAI22": lambda a1, a2, b1, b2: 1 - ((a1 | a2) & (b1 | b2)),
+    "AOI221": lambda a1, a2, b1, b2, c: 1 - ((a1 & a2) | (b1 & b2) | c),
+    "AOI222": lambda a1, a2, b1, b2, c1, c2: 1 - ((a1 & a2) | (b1 & b2) | (c1 & c2)),
 }
 
 
