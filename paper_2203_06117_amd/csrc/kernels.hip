@@ -67,6 +67,28 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
     return x;
 }
 
+// Sum of a 64-bit value over the 64 lanes (every lane gets it): the
+// inclusive scan on both halves, carrying the low half's overflow.
+__device__ __forceinline__ int64_t wave_sum64(int64_t x)
+{
+    uint64_t v = (uint64_t)x;
+#define GS_SCAN64_STEP(CTRL, RM)                                                                     \
+    {                                                                                                \
+        const uint32_t lo = dpp0<CTRL, RM>((uint32_t)v), hi = dpp0<CTRL, RM>((uint32_t)(v >> 32)); \
+        v += ((uint64_t)hi << 32) | lo;                                                              \
+    }
+    GS_SCAN64_STEP(0x111, 0xf)
+    GS_SCAN64_STEP(0x112, 0xf)
+    GS_SCAN64_STEP(0x114, 0xf)
+    GS_SCAN64_STEP(0x118, 0xf)
+    GS_SCAN64_STEP(0x142, 0xa)
+    GS_SCAN64_STEP(0x143, 0xc)
+#undef GS_SCAN64_STEP
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, kLanes - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), kLanes - 1);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Value of lane-1 in every lane (0 in lane 0): wave_shr:1.
 __device__ __forceinline__ uint32_t wave_shr1(uint32_t x)
 {
@@ -238,19 +260,17 @@ hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n
 // --------------------------------------------------------------------------
 // Stimulus expansion (the input restructuring GATSPI does before its
 // kernels, Section 4): absolute toggle times of input i become the
-// (input, tile) chunks of the window, in cycle-local time, with the
-// pre-cycle value of every cycle in the chunk mask.  Also adds the inputs'
-// SAIF counts.
+// (input, tile) chunks of the window, in cycle-local time, with every
+// cycle's pre-cycle value in bit 15 of its lane end (and in the chunk
+// mask).  Also adds the inputs' SAIF counts.
+//
+// One wave handles one input over an aligned group of kExpandGroup tiles.
+// The group's toggles are one sorted range of the input's toggle list, and
+// in the output they keep that order (cycle by cycle, which is lane after
+// lane, chunk after chunk), so the wave writes them as one contiguous,
+// coalesced range: lane k of a row handles toggle k.  Per-cycle counts come
+// from an LDS histogram of the toggles' cycle indices.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int64_t lower_bound64(const int64_t *__restrict__ a, int64_t lo, int64_t hi, int64_t key)
-{
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
 
 // Tiles an expansion wave handles: the chunks of one input in an aligned
 // group of this many tiles are placed one after another in the arena, as
@@ -258,14 +278,36 @@ __device__ __forceinline__ int64_t lower_bound64(const int64_t *__restrict__ a, 
 // pin's group of chunks as one range.
 constexpr uint32_t kExpandGroup = 4;
 
+// First index in [a, b) whose value is >= key (b if none), searched by the
+// whole wave: 64 samples per step narrow the range 64-fold.  Every lane
+// gets the same result.
+__device__ __forceinline__ int64_t wave_lower_bound(const int64_t *v, int64_t a, int64_t b, int64_t key, int lane)
+{
+    while (b - a > kLanes) {
+        const int64_t stride = (b - a + kLanes - 1) / kLanes;
+        const int64_t pos = a + (int64_t)lane * stride;
+        const bool below = pos < b && *glob(v + pos) < key;
+        const int c = __popcll(__ballot(below));           // the samples below key are a prefix
+        if (c == 0) return a;
+        const int64_t na = a + (int64_t)(c - 1) * stride + 1;
+        const int64_t nb = a + (int64_t)c * stride;
+        a = na;
+        b = nb < b ? nb : b;
+    }
+    const bool below = a + lane < b && *glob(v + a + lane) < key;
+    return a + __popcll(__ballot(below));
+}
+
 __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0_p,
                                                      uint32_t salt, uint64_t n_waves)
 {
+    extern __shared__ uint32_t ex_hist[];                   // kExpandGroup * 64 counters per wave
     const int32_t cycle0 = *glob(cycle0_p);
     const int lane = threadIdx.x & (kLanes - 1);
     const uint32_t wib = uniform(threadIdx.x / kLanes);
     const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + wib;
     if (w >= n_waves) return;
+    uint32_t *hist = ex_hist + wib * (kExpandGroup * kLanes);
     const uint32_t ntile = (uint32_t)win.n_tiles;
     const uint32_t ngrp = (ntile + kExpandGroup - 1) / kExpandGroup;
     const uint32_t i = uniform((uint32_t)(w / ngrp));
@@ -273,109 +315,94 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     const uint32_t nt = min(kExpandGroup, ntile - t0);
     const int64_t T = st.period;
     const int64_t lo = *kons(st.toggle_ptr + i), hi = *kons(st.toggle_ptr + i + 1);
-    // each lane's toggle range [s, s + cnt) in every tile of the group: the
-    // tile's toggles first (wave-uniform search), then the lane's cycle
-    // inside that short range
-    int64_t s[kExpandGroup];
-    uint32_t cnt[kExpandGroup], incl[kExpandGroup], total[kExpandGroup];
-    uint64_t mask[kExpandGroup];
-    uint32_t bound = 0;
-    int64_t ta = lo;
+    const uint32_t init_i = *kons(st.init + i) & 1u;
+    // cycles [c_lo, c_hi) of the window, times [g0, g1)
+    const int32_t c_lo = (int32_t)(t0 * kLanes);
+    const int32_t c_hi = min((int32_t)((t0 + nt) * kLanes), win.n_cycles);
+    const int64_t g0 = (int64_t)(cycle0 + c_lo) * T;
+    const int64_t g1 = (int64_t)(cycle0 + c_hi) * T;
+    const int64_t ga = wave_lower_bound(st.toggle_ps, lo, hi, g0, lane);
+    const int64_t gz = wave_lower_bound(st.toggle_ps, ga, hi, g1, lane);
+    const uint32_t n = (uint32_t)(gz - ga);
+
 #pragma unroll
-    for (uint32_t u = 0; u < kExpandGroup; u++) {
-        s[u] = 0;
-        cnt[u] = 0;
-        incl[u] = 0;
-        total[u] = 0;
-        mask[u] = 0;
-        if (u >= nt) continue;
-        const uint32_t tile = t0 + u;
-        const int32_t lc = (int32_t)(tile * kLanes + lane);
-        const bool active = lc < win.n_cycles;
-        const int64_t c0 = (int64_t)(cycle0 + lc) * T;
-        const int64_t tile_t0 = (int64_t)(cycle0 + (int32_t)(tile * kLanes)) * T;
-        int64_t tb = hi;
-        while (ta < tb) {
-            const int64_t mid = (ta + tb) >> 1;
-            if (*kons(st.toggle_ps + mid) < tile_t0) ta = mid + 1;
-            else tb = mid;
-        }
-        int64_t tz = ta;
-        tb = hi;
-        while (tz < tb) {
-            const int64_t mid = (tz + tb) >> 1;
-            if (*kons(st.toggle_ps + mid) < tile_t0 + kLanes * T) tz = mid + 1;
-            else tb = mid;
-        }
-        int64_t a = 0, e = 0;
-        if (active) {
-            a = lower_bound64(st.toggle_ps, ta, tz, c0);
-            e = lower_bound64(st.toggle_ps, a, tz, c0 + T);
-        }
-        s[u] = a;
-        cnt[u] = (uint32_t)(e - a);
-        const int v0 = active ? (int)((*kons(st.init + i) + (uint64_t)(a - lo)) & 1) : 0;
-        incl[u] = wave_incl_scan(cnt[u]);
-        total[u] = (uint32_t)lane63(incl[u]);
-        mask[u] = __ballot(v0 != 0);
-        bound += total[u];
-        ta = tz;
-    }
+    for (uint32_t k = 0; k < kExpandGroup; k++) hist[k * kLanes + lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
     // one arena reservation for the group's chunks
     const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
     uint64_t b = 0;
     bool ok = true;
-    if (bound > 0) {
+    if (n > 0) {
         if (lane == 0)
-            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)bound,
+            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)n,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         b = uniform64(b);
-        if (b + bound > win.slice_words) {
+        if (b + n > win.slice_words) {
             if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok = false;
         }
     }
-    uint64_t base = win.arena_off + (uint64_t)stripe * win.slice_words + b;
-    uint32_t tc = 0, nact = 0;
-    int32_t t1_lane = 0;
-#pragma unroll
-    for (uint32_t u = 0; u < kExpandGroup; u++) {
-        if (u >= nt) continue;
+    const uint64_t base = win.arena_off + (uint64_t)stripe * win.slice_words + b;
+    // toggles, one per lane and row: cycle index (group-relative), local time,
+    // the T1 term of the edge, and the group's output word
+    const double inv_t = 1.0 / (double)T;
+    int64_t s1 = 0;                                         // sum of -t (rising) / +t (falling) over edges
+    for (uint32_t r = 0; r < n; r += kLanes) {
+        const uint32_t k = r + (uint32_t)lane;
+        if (k < n) {
+            const int64_t t = *glob(st.toggle_ps + ga + k);
+            const uint32_t d = (uint32_t)(t - g0);         // < kExpandGroup * 64 * T <= 2^32
+            uint32_t cyc = (uint32_t)((double)d * inv_t);
+            if ((uint64_t)cyc * (uint64_t)T > d) cyc--;     // the quotient from the reciprocal may be one high
+            else if ((uint64_t)(cyc + 1) * (uint64_t)T <= d) cyc++;
+            const int32_t tl = (int32_t)(d - cyc * (uint32_t)T);
+            atomicAdd(&hist[cyc], 1u);
+            if (ok) *glob(win.times + base + k) = tl;
+            // value after this edge: the input's initial value flipped once per toggle so far
+            const uint32_t after = init_i ^ (uint32_t)((ga + k - lo + 1) & 1);
+            s1 += after ? -tl : tl;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    uint32_t before = 0;                                    // group toggles in earlier tiles
+    uint32_t nact = 0;
+    int64_t zt = 0;                                         // final values x T over the lane's cycles
+    for (uint32_t u = 0; u < nt; u++) {
         const uint32_t tile = t0 + u;
-        const int32_t lc = (int32_t)(tile * kLanes + lane);
-        const bool active = lc < win.n_cycles;
-        const int64_t c0 = (int64_t)(cycle0 + lc) * T;
+        const bool active = (int32_t)(tile * kLanes) + lane < win.n_cycles;
+        const uint32_t cnt = active ? hist[u * kLanes + lane] : 0u;
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = (uint32_t)lane63(incl);
+        const uint32_t excl = before + incl - cnt;          // group toggles before this cycle
+        const uint32_t init = active ? init_i ^ (uint32_t)((ga - lo + excl) & 1) : 0u;
         bool okc = ok;
-        if (total[u] > kMaxChunk) {
+        if (total > kMaxChunk) {
             if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             okc = false;
         }
         const uint64_t ci = (uint64_t)i * ntile + tile;
-        const uint32_t init = (uint32_t)((mask[u] >> lane) & 1);
-        *glob(win.ends + ci * kLanes + lane) = (uint16_t)((okc ? incl[u] : 0u) | (init << kEndInitShift));
+        *glob(win.ends + ci * kLanes + lane) = (uint16_t)((okc ? incl : 0u) | (init << kEndInitShift));
+        const uint64_t mask = __ballot(init != 0);
         if (lane == 0) {
             ChunkHdr h;
-            h.off = okc ? base : 0;
-            h.mask = mask[u];
+            h.off = okc ? base + before : 0;
+            h.mask = mask;
             *glob(win.hdr + ci) = h;
         }
-        // time at 1 inside [0, T): final value * T - rising-edge times + falling-edge times
-        int v = (int)((mask[u] >> lane) & 1), acc1 = 0;
-        for (uint32_t j = 0; j < cnt[u]; j++) {
-            const int32_t tl = (int32_t)(st.toggle_ps[s[u] + j] - c0);
-            if (okc) *glob(win.times + base + (incl[u] - cnt[u]) + j) = tl;
-            v ^= 1;
-            acc1 += v ? -tl : tl;
-        }
-        base += total[u];
-        tc += total[u];
         nact += (uint32_t)__popcll(__ballot(active));
-        t1_lane += active ? v * (int32_t)T + acc1 : 0;
+        zt += active ? (int64_t)(init ^ (cnt & 1u)) * T : 0;
+        before += total;
     }
-    const int32_t sum1 = lane63(wave_incl_scan((uint32_t)t1_lane));
+    const int64_t sum1 = wave_sum64(zt + s1);
     if (lane == 0) {
-        __hip_atomic_fetch_add(glob(acc.tc + i), (unsigned long long)tc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(glob(acc.t1 + i), (unsigned long long)(int64_t)sum1, __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(glob(acc.tc + i), (unsigned long long)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(glob(acc.t1 + i), (unsigned long long)sum1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(acc.t0 + i), (unsigned long long)((int64_t)nact * T - sum1), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -388,7 +415,8 @@ hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *c
     if (n_waves == 0) return hipSuccess;
     const int wpb = 4;
     uint64_t blocks = (n_waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, st, win, acc, cycle0, salt,
+    const size_t lds = (size_t)wpb * kExpandGroup * kLanes * sizeof(uint32_t);
+    hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, st, win, acc, cycle0, salt,
                        n_waves);
     return hipGetLastError();
 }
@@ -955,11 +983,11 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             }
         }
     }
-    const int32_t sum1 = lane63(wave_incl_scan((uint32_t)t1_lane));
+    const int64_t sum1 = wave_sum64((int64_t)t1_lane);    // up to 64 lanes x 64 tiles x T: beyond 32 bits
     if (lane == 0) {
         __hip_atomic_fetch_add(glob(sg.saif.tc + g.out), (unsigned long long)tc_sum, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(glob(sg.saif.t1 + g.out), (unsigned long long)(int64_t)sum1, __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(glob(sg.saif.t1 + g.out), (unsigned long long)sum1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(sg.saif.t0 + g.out), (unsigned long long)((int64_t)nact_sum * T - sum1),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -271,11 +271,17 @@ class GateSim:
     def simulate(self, design, stim, cycle_begin, cycle_end):
         self._chk(_lib.gs_simulate(self._h, design, stim, int(cycle_begin), int(cycle_end)))
 
-    def read_saif(self, design, reset=False):
+    def read_saif(self, design, reset=False, out=None):
+        """TC, T0, T1 per net.  ``out``: three caller-owned int64 arrays of
+        n_nets entries to fill instead of new ones (page-locked arrays let the
+        copy run as one DMA)."""
         n = self.n_nets[design]
-        tc = np.zeros(n, dtype=np.int64)
-        t0 = np.zeros(n, dtype=np.int64)
-        t1 = np.zeros(n, dtype=np.int64)
+        if out is None:
+            out = tuple(np.zeros(n, dtype=np.int64) for _ in range(3))
+        for a in out:
+            if a.dtype != np.int64 or a.shape != (n,) or not a.flags["C_CONTIGUOUS"] or not a.flags["WRITEABLE"]:
+                raise ValueError(f"read_saif: out arrays must be writable contiguous int64[{n}]")
+        tc, t0, t1 = out
         self._chk(_lib.gs_read_saif(self._h, design, _p(tc), _p(t0), _p(t1), 1 if reset else 0))
         return tc, t0, t1
 

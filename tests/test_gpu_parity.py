@@ -173,6 +173,17 @@ def test_wide_cells(G, opt):
             assert g_ == o_, (n, c)
 
 
+def test_long_period(G):
+    """The longest allowed period: a wave's T1 sum over its tiles passes 2^32
+    picoseconds, so the per-wave reductions must not wrap."""
+    T = (1 << 24) - 1
+    w = synth.small_random(93, 400, 12, 10, 300, T, 0.5, 5, 60, cond_frac=0.2, extra=2, extra_p=0.3)
+    ref = oracle.simulate(w)
+    assert int(ref["t1"].max()) > (1 << 32)
+    for opt in (dict(), dict(tiles_per_wave=16)):
+        assert_same(w, gpu_saif(G, w, **opt), ref, f"long period {opt}")
+
+
 def test_cycle_subranges(G):
     """Accumulating disjoint sub-ranges equals the whole range; a range can
     start and end anywhere (ragged tiles on both sides)."""
