@@ -95,6 +95,22 @@ def run_scale(args, torch, synth, GateSim):
         torch.cuda.synchronize()
         log(f"calibration kernel: {n * 4} bytes read, {n * 4} bytes written")
         del a, b
+    copy_gbs = None
+    if not args.no_timing:
+        # achievable HBM bandwidth on this device: a 2 GiB device-to-device copy
+        src = torch.empty(1 << 29, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"copy kernel: {copy_gbs:.0f} GB/s (read + write)")
+        del src, dst
+        torch.cuda.empty_cache()
     for i in range(args.warmup):
         sim.simulate(d, s, 0, C)
         sim.read_saif(d, reset=True)
@@ -123,8 +139,11 @@ def run_scale(args, torch, synth, GateSim):
         avg_launch_s = st["gate_eval_ms"] / 1e3 / launches
         per_launch_bytes = alg_bytes_step * args.steps / launches
         achieved = per_launch_bytes / avg_launch_s / 1e9
+        traffic = measured_traffic()
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_gbs": round(traffic / avg_launch_s / 1e9, 1) if traffic else None,
+                    "copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
                     "kernel": "gate_eval_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
                     "launches": launches, "bytes_per_launch": round(per_launch_bytes),
                     "bytes_per_gate_cycle": round(alg_bytes_step / (Gn * C), 3)}

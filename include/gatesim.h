@@ -164,7 +164,9 @@ gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_b
 
 /* Copies the design's accumulated SAIF counts, n_inputs + n_gates entries
  * each, into caller arrays (any may be NULL); nonzero reset zeroes the
- * accumulators afterwards. */
+ * accumulators afterwards.  Page-locked arrays (hipHostMalloc) are filled
+ * by one DMA each; pageable ones are staged by the HIP runtime, which is
+ * several times slower for large designs. */
 gs_status gs_read_saif(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0, int64_t *t1, int32_t reset);
 
 /* Debug/spot-check read of one net's waveform in one cycle of the most
