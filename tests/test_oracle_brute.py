@@ -49,6 +49,11 @@ def test_oracle_matches_brute(mode):
         assert r["t1"].tolist() == t1, seed
         for (n, c), (pinit, ptimes, _) in zip(probes, r["probes"]):
             assert (pinit, ptimes) == waves[(n, c)], (seed, n, c)
+        # glitch toggles from the brute model's lists: all but the cycle's functional edge
+        ig = [0] * N
+        for (n, c), (_, times) in waves.items():
+            ig[n] += len(times) - len(times) % 2
+        assert r["ig"].tolist() == ig, seed
         n_ok += 1
     assert n_ok == 120
 

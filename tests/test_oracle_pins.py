@@ -90,6 +90,7 @@ def test_inv_buf_chains():
                 assert r["probes"][pi][0] == out_v
                 assert r["probes"][pi][1] == out_edges, (trial, c, i)
                 v, edges = out_v, out_edges
+        assert r["ig"].tolist() == [0] * (n + 1)            # at most one toggle per cycle: nothing is a glitch
 
 
 def _pulse_grid(cell, init):
@@ -153,12 +154,16 @@ def test_xor_glitch_generator():
         arcs = [(0, 0, -1, 0, a, a), (1, 0, -1, 0, b, b),
                 (2, 0, -1, 0, rx, fx), (2, 1, -1, 0, rx, fx)]
         w = work(1, gates, arcs, [[10]], [0], period=100)
-        _, times, _ = run1(w, [(3, 0)])["probes"][0]
+        r = run1(w, [(3, 0)])
+        _, times, _ = r["probes"][0]
         lo, hi = min(a, b), max(a, b)
         if a == b or hi - lo < rx:
             assert times == [], (a, b, rx, fx)
+            assert r["ig"][3] == 0
         else:
             assert times == [10 + lo + rx, 10 + hi + fx], (a, b, rx, fx)
+            assert r["ig"][3] == 2 and r["tc"][3] == 2      # the whole pulse is a glitch
+        assert r["ig"][:3].tolist() == [0, 0, 0]            # one functional edge on the input and buffers
 
 
 def test_msi_min_delay():
