@@ -142,6 +142,10 @@ def run_scale(args, torch, synth, GateSim):
     gate_cycles = Gn * C * args.steps
     log(f"{args.steps} steps in {elapsed:.3f}s")
     tc = saif[0]
+    # glitch share of the output toggles, read once after the timed steps
+    sim.simulate(d, s, 0, min(C, 1000))
+    g_tc, _, _, g_ig = sim.read_saif_ig(d, reset=True)
+    glitch_share = float(g_ig[net["n_inputs"]:].sum()) / max(1.0, float(g_tc[net["n_inputs"]:].sum()))
     n_tiles_total = sum((min(window, C - c0) + 63) // 64 for c0 in range(0, C, window))
     alg_bytes_step = algorithmic_bytes(net, tc, C, n_tiles_total)
     launches = st["gate_eval_launches"]
@@ -201,6 +205,7 @@ def run_scale(args, torch, synth, GateSim):
                    "waves_per_block": args.wpb, "tiles_per_wave": args.tpw},
         "kernel_gate_cycles_per_s": round(gate_cycles / (st["gate_eval_ms"] / 1e3), 1) if roofline else None,
         "transitions_per_gate_cycle": round(a_bar, 4),
+        "glitch_share_of_gate_toggles": round(glitch_share, 4),
         "spilled_lanes": st["spilled_lanes"],
         "window_retries": st["window_retries"],
         "roofline": roofline,

@@ -169,6 +169,13 @@ gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_b
  * several times slower for large designs. */
 gs_status gs_read_saif(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0, int64_t *t1, int32_t reset);
 
+/* As gs_read_saif, and also the glitch toggles per net (SAIF's IG; the
+ * paper's SAIF output, Section 3): a cycle whose list has L edges adds
+ * L - (L mod 2), every edge but the one functional edge of an odd list.
+ * Any array may be NULL; reset zeroes all four accumulators. */
+gs_status gs_read_saif_ig(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0, int64_t *t1, int64_t *ig,
+                          int32_t reset);
+
 /* Debug/spot-check read of one net's waveform in one cycle of the most
  * recently simulated window of (design, stim): *init gets the value at
  * t = 0, *n the number of edges, times[0 .. min(*n, cap)) the edge times in
@@ -281,6 +288,7 @@ typedef struct {
     const int64_t *tc;      /* library-owned until gs_release(ticket) */
     const int64_t *t0;
     const int64_t *t1;
+    const int64_t *ig;      /* glitch toggles, as gs_read_saif_ig */
     int64_t  gate_cycles;   /* gates x cycles re-simulated for this request */
     uint64_t t_submit_ns;   /* CLOCK_MONOTONIC */
     uint64_t t_admit_ns;

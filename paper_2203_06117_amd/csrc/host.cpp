@@ -442,11 +442,11 @@ extern "C" gs_status gs_load_netlist(gs_ctx *ctx, int32_t n_inputs, int32_t n_ga
     d->wr.assign(d->F, 0);
     d->wf.assign(d->F, 0);
     void *p;
-    if ((st = dev_alloc(ctx, &p, sizeof(unsigned long long) * 3 * std::max(1, d->N)))) { delete d; return st; }
+    if ((st = dev_alloc(ctx, &p, sizeof(unsigned long long) * kSaifArrays * std::max(1, d->N)))) { delete d; return st; }
     d->d_saif = (unsigned long long *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(unsigned long long) * 3 * std::max(1, d->N)))) { gs_dev_free(d->d_saif); delete d; return st; }
+    if ((st = dev_alloc(ctx, &p, sizeof(unsigned long long) * kSaifArrays * std::max(1, d->N)))) { gs_dev_free(d->d_saif); delete d; return st; }
     d->d_stage = (unsigned long long *)p;
-    hipError_t e = hipMemsetAsync(d->d_saif, 0, sizeof(unsigned long long) * 3 * std::max(1, d->N), ctx->stream);
+    hipError_t e = hipMemsetAsync(d->d_saif, 0, sizeof(unsigned long long) * kSaifArrays * std::max(1, d->N), ctx->stream);
     if (e != hipSuccess) { gs_dev_free(d->d_saif); gs_dev_free(d->d_stage); delete d; return gs_fail(ctx, GS_E_DEVICE, "memset failed"); }
     ctx->designs.push_back(d);
     st = levelize(ctx, d);
@@ -726,6 +726,12 @@ hipEvent_t gs_event(gs_ctx *ctx, size_t i)
 
 extern "C" gs_status gs_read_saif(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0, int64_t *t1, int32_t reset)
 {
+    return gs_read_saif_ig(ctx, design, tc, t0, t1, nullptr, reset);
+}
+
+extern "C" gs_status gs_read_saif_ig(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0, int64_t *t1, int64_t *ig,
+                                     int32_t reset)
+{
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
     Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
@@ -736,7 +742,8 @@ extern "C" gs_status gs_read_saif(gs_ctx *ctx, int32_t design, int64_t *tc, int6
         if (tc) HIPCHK(hipMemcpyAsync(tc, d->d_saif, n * 8, hipMemcpyDeviceToHost, hs));
         if (t0) HIPCHK(hipMemcpyAsync(t0, d->d_saif + n, n * 8, hipMemcpyDeviceToHost, hs));
         if (t1) HIPCHK(hipMemcpyAsync(t1, d->d_saif + 2 * n, n * 8, hipMemcpyDeviceToHost, hs));
-        if (reset) HIPCHK(launch_fill_u64(d->d_saif, 3 * n, 0ull, hs));
+        if (ig) HIPCHK(hipMemcpyAsync(ig, d->d_saif + 3 * n, n * 8, hipMemcpyDeviceToHost, hs));
+        if (reset) HIPCHK(launch_fill_u64(d->d_saif, kSaifArrays * n, 0ull, hs));
     }
     HIPCHK(hipStreamSynchronize(hs));
     return GS_OK;

@@ -40,7 +40,7 @@ struct Design {
     int32_t *d_level = nullptr;
     gs::GateRec *d_gates = nullptr;
     gs::PinRec *d_pins = nullptr;
-    unsigned long long *d_saif = nullptr;    // tc[N], t0[N], t1[N] (SaifAcc order)
+    unsigned long long *d_saif = nullptr;    // tc[N], t0[N], t1[N], ig[N] (SaifAcc order)
     unsigned long long *d_stage = nullptr;   // per-window staging, same layout
 };
 

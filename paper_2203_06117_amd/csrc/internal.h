@@ -76,11 +76,22 @@ struct WinView {
 constexpr int kMaxStripes = 512;
 constexpr int kBumpStride = 32;             // u64 counters between stripes (256 B)
 
+// SAIF accumulators, N entries each and contiguous in this order: toggle
+// count, time at 0, time at 1, glitch toggles (edges of a cycle beyond its
+// functional one).
+constexpr int kSaifArrays = 4;
 struct SaifAcc {
     unsigned long long *tc;
     unsigned long long *t0;
     unsigned long long *t1;
+    unsigned long long *ig;
 };
+
+// The accumulators of N nets starting at base.
+inline SaifAcc saif_view(unsigned long long *base, size_t n)
+{
+    return SaifAcc{base, base + n, base + 2 * n, base + 3 * n};
+}
 
 // One piece of a gate-evaluation launch: the gates [gate_begin,
 // gate_begin + n_gates) of one level of one instance, all tiles of its

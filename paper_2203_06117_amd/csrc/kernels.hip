@@ -371,7 +371,7 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     uint32_t before = 0;                                    // group toggles in earlier tiles
-    uint32_t nact = 0;
+    uint32_t nact = 0, glitch = 0;
     int64_t zt = 0;                                         // final values x T over the lane's cycles
     for (uint32_t u = 0; u < nt; u++) {
         const uint32_t tile = t0 + u;
@@ -397,11 +397,15 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
         }
         nact += (uint32_t)__popcll(__ballot(active));
         zt += active ? (int64_t)(init ^ (cnt & 1u)) * T : 0;
+        glitch += total - (uint32_t)__popcll(__ballot(cnt & 1u));   // all but one edge of odd lists
         before += total;
     }
     const int64_t sum1 = wave_sum64(zt + s1);
     if (lane == 0) {
         __hip_atomic_fetch_add(glob(acc.tc + i), (unsigned long long)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (glitch)
+            __hip_atomic_fetch_add(glob(acc.ig + i), (unsigned long long)glitch, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(acc.t1 + i), (unsigned long long)sum1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(acc.t0 + i), (unsigned long long)((int64_t)nact * T - sum1), __ATOMIC_RELAXED,
@@ -755,7 +759,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
     const uint16_t *cesrc = (REMAP && cres) ? win.rd_ends : win.ends;
 
     const uint32_t out_lane = out_base + lane;
-    uint32_t tc_sum = 0, nact_sum = 0;
+    uint32_t tc_sum = 0, nact_sum = 0, ig_sum = 0;
     int32_t t1_lane = 0;
     for (uint32_t gb = 0; gb < ntl; gb += GT) {
         const uint32_t ng = min(GT, ntl - gb);
@@ -970,6 +974,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             }
             z = y0 ^ (cnt & 1);                      // every kept edge toggles the output
             tc_sum += total;
+            ig_sum += total - (uint32_t)__popcll(__ballot(cnt & 1));   // a cycle's edges beyond its functional one
             nact_sum += (uint32_t)__popcll(__ballot(active));
             t1_lane += active ? z * T + acc : 0;
 #pragma unroll
@@ -987,6 +992,9 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
     if (lane == 0) {
         __hip_atomic_fetch_add(glob(sg.saif.tc + g.out), (unsigned long long)tc_sum, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+        if (ig_sum)
+            __hip_atomic_fetch_add(glob(sg.saif.ig + g.out), (unsigned long long)ig_sum, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(sg.saif.t1 + g.out), (unsigned long long)sum1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(sg.saif.t0 + g.out), (unsigned long long)((int64_t)nact_sum * T - sum1),
@@ -1212,6 +1220,7 @@ __global__ void saif_zero_kernel(const GateRec *__restrict__ gates, uint32_t n, 
     acc.tc[o] = 0;
     acc.t0[o] = 0;
     acc.t1[o] = 0;
+    acc.ig[o] = 0;
 }
 
 hipError_t launch_saif_zero(const GateRec *gates, uint32_t n, SaifAcc acc, hipStream_t s)

@@ -78,7 +78,7 @@ void build_steps(gs_ctx *ctx, const std::vector<Piece> &pieces, const std::vecto
             g.n_gates = n_gates;
             g.salt = (uint32_t)salt;
             g.win = views[i];
-            g.saif = SaifAcc{p.d->d_stage, p.d->d_stage + p.d->N, p.d->d_stage + 2 * (size_t)p.d->N};
+            g.saif = saif_view(p.d->d_stage, (size_t)p.d->N);
             const uint64_t nw = (uint64_t)n_gates * ngroup;
             waves += nw;
             salt += (nw + tu.wpb - 1) / tu.wpb * tu.tpw;
@@ -107,12 +107,12 @@ gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pi
     size_t ev = 0;
     HIPCHK(launch_fill_u64(ctx->d_misc, 4, 0ull, hs));
     HIPCHK(launch_fill_u64(ctx->d_bump, (uint64_t)kMaxStripes * kBumpStride, 0ull, hs));
-    for (Design *d : designs) HIPCHK(launch_fill_u64(d->d_stage, 3 * (uint64_t)d->N, 0ull, hs));
+    for (Design *d : designs) HIPCHK(launch_fill_u64(d->d_stage, kSaifArrays * (uint64_t)d->N, 0ull, hs));
     if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     for (size_t i = 0; i < pieces.size(); i++) {
         const Piece &p = pieces[i];
         StimView sv{p.s->d_init, p.s->d_tp, p.s->d_ts, p.d->I, p.s->period};
-        SaifAcc stage{p.d->d_stage, p.d->d_stage + p.d->N, p.d->d_stage + 2 * (size_t)p.d->N};
+        SaifAcc stage = saif_view(p.d->d_stage, (size_t)p.d->N);
         HIPCHK(launch_expand(sv, views[i], stage, ctx->d_c0 + i, (uint32_t)(i * 977), hs));
     }
     if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
@@ -125,7 +125,7 @@ gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pi
     }
     if (commit)
         for (Design *d : designs)
-            HIPCHK(launch_add_u64_guarded(d->d_saif, d->d_stage, 3 * (uint64_t)d->N, (const unsigned int *)(ctx->d_misc + 1), hs));
+            HIPCHK(launch_add_u64_guarded(d->d_saif, d->d_stage, kSaifArrays * (uint64_t)d->N, (const unsigned int *)(ctx->d_misc + 1), hs));
     return GS_OK;
 }
 

@@ -85,7 +85,7 @@ struct Resident {
     Region region;
     ChunkHdr *hdr;
     uint16_t *ends;
-    unsigned long long *saif;            // tc, t0, t1 of the resident window
+    unsigned long long *saif;            // SAIF accumulators of the resident window (SaifAcc order)
 };
 
 struct Req {
@@ -96,7 +96,7 @@ struct Req {
     gs_status status = GS_OK;
     std::string err;
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
-    std::vector<int64_t> tc, t0, t1;
+    std::vector<int64_t> tc, t0, t1, ig;
     int64_t gate_cycles = 0;
     // execution
     Design *d = nullptr;
@@ -195,7 +195,7 @@ uint64_t region_bytes(uint64_t rows, int32_t tiles, uint64_t words, uint64_t n_n
     b += align256(rows * tiles * sizeof(ChunkHdr));
     b += align256(rows * tiles * kLanes * sizeof(uint16_t));
     b += align256(words * sizeof(int32_t));
-    b += align256(3 * n_nets * sizeof(unsigned long long));
+    b += align256(kSaifArrays * n_nets * sizeof(unsigned long long));
     b += align256((uint64_t)kMaxStripes * kBumpStride * sizeof(unsigned long long));
     b += 256;                                               // flags + first cycle
     if (edit) {
@@ -216,7 +216,7 @@ void layout(ServeState *S, Req &q, uint64_t rows)
     const uint64_t arena_off_bytes = o;
     o += align256(q.arena_words * sizeof(int32_t));
     unsigned long long *saif = at<unsigned long long>(S, o);
-    o += align256(3 * (uint64_t)q.d->N * sizeof(unsigned long long));
+    o += align256(kSaifArrays * (uint64_t)q.d->N * sizeof(unsigned long long));
     q.bump = at<unsigned long long>(S, o);
     o += align256((uint64_t)kMaxStripes * kBumpStride * sizeof(unsigned long long));
     q.flags = at<unsigned int>(S, o);
@@ -236,7 +236,7 @@ void layout(ServeState *S, Req &q, uint64_t rows)
     q.view.n_tiles = q.tiles;
     q.view.n_cycles = q.cycles;
     q.view.period = q.s->period;
-    q.acc = SaifAcc{saif, saif + q.d->N, saif + 2 * (size_t)q.d->N};
+    q.acc = saif_view(saif, (size_t)q.d->N);
     if (q.r.kind == GS_REQ_EDIT) {
         GateRec *g = at<GateRec>(S, o);
         o += align256((uint64_t)q.n_cone * sizeof(GateRec));
@@ -266,14 +266,15 @@ gs_status start_request(gs_ctx *ctx, ServeState *S, Req &q, std::string &err)
     SCHK(launch_fill_u32(q.flags, 16, 0u, hs));
     SCHK(launch_fill_u64(q.bump, (uint64_t)kMaxStripes * kBumpStride, 0ull, hs));
     if (q.r.kind == GS_REQ_WINDOW) {
-        SCHK(launch_fill_u64(q.acc.tc, 3 * (uint64_t)q.d->N, 0ull, hs));
+        SCHK(launch_fill_u64(q.acc.tc, kSaifArrays * (uint64_t)q.d->N, 0ull, hs));
         SCHK(launch_fill_u32((unsigned int *)q.d_c0, 1, (unsigned int)q.c0, hs));
         StimView sv{q.s->d_init, q.s->d_tp, q.s->d_ts, q.d->I, q.s->period};
         SCHK(launch_expand(sv, q.view, q.acc, q.d_c0, (uint32_t)(S->salt++ * 131), hs));
     } else {
         const Resident &R = S->res[q.res_idx];
         SCHK(hipStreamWaitEvent(hs, q.ev_prep, 0));
-        SCHK(hipMemcpyAsync(q.acc.tc, R.saif, 3 * sizeof(unsigned long long) * q.d->N, hipMemcpyDeviceToDevice, hs));
+        SCHK(hipMemcpyAsync(q.acc.tc, R.saif, kSaifArrays * sizeof(unsigned long long) * q.d->N, hipMemcpyDeviceToDevice,
+                            hs));
         SCHK(launch_saif_zero(q.gates, q.n_cone, q.acc, hs));
     }
     (void)ctx;
@@ -609,7 +610,7 @@ void serve_loop(gs_ctx *ctx, ServeState *S)
             if (pb < 0) break;                             // a buffer frees up once a finalize completes
             q->pinned = pb;
             char *h = (char *)S->pinned[pb];
-            const size_t n3 = 3 * sizeof(unsigned long long) * q->d->N;
+            const size_t n3 = kSaifArrays * sizeof(unsigned long long) * q->d->N;
             hipError_t e = hipMemcpyAsync(h, q->acc.tc, n3, hipMemcpyDeviceToHost, S->st);
             if (e == hipSuccess) e = hipMemcpyAsync(h + n3, q->flags, 16, hipMemcpyDeviceToHost, S->st);
             if (e == hipSuccess) e = hipMemcpyAsync(h + n3 + 16, q->bump, sizeof(unsigned long long) * kMaxStripes * kBumpStride,
@@ -638,17 +639,19 @@ void serve_loop(gs_ctx *ctx, ServeState *S)
             // results are copied out of the pinned buffer before taking the lock
             const char *h = (const char *)S->pinned[q->pinned];
             const size_t N = (size_t)q->d->N;
-            const unsigned int *fl = (const unsigned int *)(h + 3 * 8 * N);
-            const unsigned long long *hb = (const unsigned long long *)(h + 3 * 8 * N + 16);
+            const unsigned int *fl = (const unsigned int *)(h + kSaifArrays * 8 * N);
+            const unsigned long long *hb = (const unsigned long long *)(h + kSaifArrays * 8 * N + 16);
             const bool good = e == hipSuccess && !fl[0] && !fl[1] && !fl[3];
             if (good) {
                 q->tc.resize(N);
                 q->t0.resize(N);
                 q->t1.resize(N);
+                q->ig.resize(N);
                 const unsigned long long *a = (const unsigned long long *)h;
                 std::memcpy(q->tc.data(), a, 8 * N);
                 std::memcpy(q->t0.data(), a + N, 8 * N);
                 std::memcpy(q->t1.data(), a + 2 * N, 8 * N);
+                std::memcpy(q->ig.data(), a + 3 * N, 8 * N);
             }
             std::lock_guard<std::mutex> lk(S->mu);
             if (e != hipSuccess) {
@@ -776,7 +779,7 @@ extern "C" gs_status gs_serve_start(gs_ctx *ctx, int32_t n_resident, const int32
     int32_t max_n = 1;
     for (Design *d : ctx->designs)
         if (d) max_n = std::max(max_n, d->N);
-    S->pinned_bytes = 3ull * 8 * max_n + 16 + 8ull * kMaxStripes * kBumpStride;
+    S->pinned_bytes = (uint64_t)kSaifArrays * 8 * max_n + 16 + 8ull * kMaxStripes * kBumpStride;
     for (int i = 0; i < kPinned; i++)
         if (hipHostMalloc(&S->pinned[i], S->pinned_bytes, hipHostMallocDefault) != hipSuccess)
             return fail(GS_E_NOMEM, "cannot allocate pinned result buffers");
@@ -887,6 +890,7 @@ extern "C" gs_status gs_poll(gs_ctx *ctx, uint64_t ticket, int32_t wait, gs_resu
         res->tc = q->status == GS_OK ? q->tc.data() : nullptr;
         res->t0 = q->status == GS_OK ? q->t0.data() : nullptr;
         res->t1 = q->status == GS_OK ? q->t1.data() : nullptr;
+        res->ig = q->status == GS_OK ? q->ig.data() : nullptr;
         res->gate_cycles = q->gate_cycles;
         res->t_submit_ns = q->t_submit;
         res->t_admit_ns = q->t_admit;

@@ -80,7 +80,8 @@ class Request(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_nets", C.c_int32), ("tc", C.POINTER(C.c_int64)),
-                ("t0", C.POINTER(C.c_int64)), ("t1", C.POINTER(C.c_int64)), ("gate_cycles", C.c_int64),
+                ("t0", C.POINTER(C.c_int64)), ("t1", C.POINTER(C.c_int64)), ("ig", C.POINTER(C.c_int64)),
+                ("gate_cycles", C.c_int64),
                 ("t_submit_ns", C.c_uint64), ("t_admit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
 
 
@@ -98,6 +99,7 @@ _SIGS = {
     "gs_load_stimulus": (I32, [P, I32, I32, I32, P, P, P, C.POINTER(I32)]),
     "gs_simulate": (I32, [P, I32, I32, I32, I32]),
     "gs_read_saif": (I32, [P, I32, P, P, P, I32]),
+    "gs_read_saif_ig": (I32, [P, I32, P, P, P, P, I32]),
     "gs_read_waveform": (I32, [P, I32, I32, I32, I32, C.POINTER(I32), P, I32, C.POINTER(I32)]),
     "gs_get_design_info": (I32, [P, I32, C.POINTER(DesignInfo)]),
     "gs_get_levels": (I32, [P, I32, P]),
@@ -285,6 +287,13 @@ class GateSim:
         self._chk(_lib.gs_read_saif(self._h, design, _p(tc), _p(t0), _p(t1), 1 if reset else 0))
         return tc, t0, t1
 
+    def read_saif_ig(self, design, reset=False):
+        """TC, T0, T1 and glitch toggles (IG) per net."""
+        n = self.n_nets[design]
+        tc, t0, t1, ig = (np.zeros(n, dtype=np.int64) for _ in range(4))
+        self._chk(_lib.gs_read_saif_ig(self._h, design, _p(tc), _p(t0), _p(t1), _p(ig), 1 if reset else 0))
+        return tc, t0, t1, ig
+
     def read_waveform(self, design, stim, net, cycle, cap=65536):
         init, n = I32(), I32()
         buf = np.zeros(cap, dtype=np.int32)
@@ -358,6 +367,7 @@ class GateSim:
             out["tc"] = np.ctypeslib.as_array(res.tc, shape=(n,)).copy()
             out["t0"] = np.ctypeslib.as_array(res.t0, shape=(n,)).copy()
             out["t1"] = np.ctypeslib.as_array(res.t1, shape=(n,)).copy()
+            out["ig"] = np.ctypeslib.as_array(res.ig, shape=(n,)).copy()
         return out
 
     def release(self, ticket):

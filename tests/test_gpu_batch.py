@@ -25,7 +25,7 @@ def say(*a):
 
 
 def same(got, ref, tag):
-    for name, a, b in zip(("tc", "t0", "t1"), got, (ref["tc"], ref["t0"], ref["t1"])):
+    for name, a, b in zip(("tc", "t0", "t1", "ig"), got, (ref["tc"], ref["t0"], ref["t1"], ref["ig"])):
         if not np.array_equal(a, b):
             bad = np.nonzero(a != b)[0]
             raise AssertionError(f"{tag}: {name} differs on {len(bad)} nets, first {bad[:6]}")
@@ -60,7 +60,7 @@ def test_graph_replays(G):
         for b in range(0, 330, 64):
             e = min(330, b + 64)
             sim.simulate(d, s, b, e)
-            got = sim.read_saif(d, reset=True)
+            got = sim.read_saif_ig(d, reset=True)
             x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
             assert float(x.sum().item()) > 0
             torch.cuda.synchronize()
@@ -80,7 +80,7 @@ def test_batch_uneven_instances(G):
         say("batch", [w["netlist"]["n_gates"] for w in works])
         sim.simulate_batch(jobs)
         for (d, s), w in zip(ids, works):
-            same(sim.read_saif(d), oracle.simulate(w), f"design {d}")
+            same(sim.read_saif_ig(d), oracle.simulate(w), f"design {d}")
 
 
 def test_batch_repeated_design_and_ranges(G):
@@ -91,7 +91,7 @@ def test_batch_repeated_design_and_ranges(G):
         jobs = [(d, s, 0, 70), (d, s, 70, 71), (d, s, 71, 200)]
         for rep in range(3):
             sim.simulate_batch(jobs)
-            same(sim.read_saif(d, reset=True), oracle.simulate(w), f"replay {rep}")
+            same(sim.read_saif_ig(d, reset=True), oracle.simulate(w), f"replay {rep}")
 
 
 def test_batch_tight_budget(G):
@@ -102,7 +102,7 @@ def test_batch_tight_budget(G):
         ids = [sim.load_work(w, cells_loaded=i > 0) for i, w in enumerate(works)]
         sim.simulate_batch([(d, s, 0, w["stimulus"]["n_cycles"]) for (d, s), w in zip(ids, works)])
         for (d, s), w in zip(ids, works):
-            same(sim.read_saif(d), oracle.simulate(w), f"design {d}")
+            same(sim.read_saif_ig(d), oracle.simulate(w), f"design {d}")
 
 
 def test_autotune_keeps_results(G):
@@ -115,4 +115,4 @@ def test_autotune_keeps_results(G):
         tc, t0, t1 = sim.read_saif(d)
         assert not tc.any() and not t1.any()                  # nothing committed while tuning
         sim.simulate_batch([(d, s, 0, 150)])
-        same(sim.read_saif(d), oracle.simulate(w), "after autotune")
+        same(sim.read_saif_ig(d), oracle.simulate(w), "after autotune")

@@ -42,15 +42,18 @@ def gpu_saif(G, w, b=0, e=None, probes=(), **opt):
     with G.GateSim(**opt) as sim:
         d, s = sim.load_work(w)
         sim.simulate(d, s, b, e)
-        tc, t0, t1 = sim.read_saif(d)
+        tc, t0, t1, ig = sim.read_saif_ig(d)
         waves = [sim.read_waveform(d, s, n, c) for n, c in probes]
         st = sim.stats()
-    return tc, t0, t1, waves, st
+    return tc, t0, t1, waves, st, ig
 
 
 def assert_same(w, got, ref, tag=""):
     tc, t0, t1 = got[:3]
-    for name, a, b in (("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"])):
+    cols = [("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"])]
+    if len(got) > 5:
+        cols.append(("ig", got[5], ref["ig"]))
+    for name, a, b in cols:
         if not np.array_equal(a, b):
             bad = np.nonzero(a != b)[0]
             raise AssertionError(f"{tag}: {name} differs on {len(bad)} nets, first {bad[:8]} "

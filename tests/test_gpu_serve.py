@@ -28,7 +28,7 @@ def say(*a):
 
 
 def same(got, ref, tag):
-    for name, a, b in zip(("tc", "t0", "t1"), got, ref):
+    for name, a, b in zip(("tc", "t0", "t1", "ig"), got, ref):
         if not np.array_equal(a, b):
             bad = np.nonzero(a != b)[0]
             raise AssertionError(f"{tag}: {name} differs on {len(bad)} nets, first {bad[:6]}")
@@ -91,7 +91,7 @@ def test_window_requests(served):
     for i, b, e, t in reqs:
         r = result_of(sim, t)
         ref = oracle.simulate(works[i], b, e)
-        same((r["tc"], r["t0"], r["t1"]), (ref["tc"], ref["t0"], ref["t1"]), f"window {i} [{b},{e})")
+        same((r["tc"], r["t0"], r["t1"], r["ig"]), (ref["tc"], ref["t0"], ref["t1"], ref["ig"]), f"window {i} [{b},{e})")
         assert r["t_submit_ns"] <= r["t_admit_ns"] <= r["t_done_ns"]
 
 
@@ -105,7 +105,7 @@ def test_edit_requests(served):
         w2 = dict(works[i], arcs=edited_arcs(works[i]["arcs"], edits))
         _, _, b, n = resident[i]
         ref = oracle.simulate(w2, b, b + n)
-        same((r["tc"], r["t0"], r["t1"]), (ref["tc"], ref["t0"], ref["t1"]), f"edit {k}")
+        same((r["tc"], r["t0"], r["t1"], r["ig"]), (ref["tc"], ref["t0"], ref["t1"], ref["ig"]), f"edit {k}")
         assert r["gate_cycles"] <= works[i]["netlist"]["n_gates"] * n
 
 
@@ -130,7 +130,7 @@ def test_alone_equals_mix(served):
     alone = []
     for p in plan:
         r = result_of(sim, submit(p))
-        alone.append((r["tc"], r["t0"], r["t1"]))
+        alone.append((r["tc"], r["t0"], r["t1"], r["ig"]))
     tickets = [None] * len(plan)
 
     def worker(lo):
@@ -144,7 +144,7 @@ def test_alone_equals_mix(served):
         t.join()
     for j, t in enumerate(tickets):
         r = result_of(sim, t)
-        same((r["tc"], r["t0"], r["t1"]), alone[j], f"request {j}")
+        same((r["tc"], r["t0"], r["t1"], r["ig"]), alone[j], f"request {j}")
 
 
 def test_bad_edit_is_rejected(served):
