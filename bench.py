@@ -8,13 +8,17 @@ gates x cycles per second over the timed steps.
 
 Also reported (one JSON line):
   roofline      algorithmic bytes of the gate-evaluation kernel / its average
-                launch time (HIP events on the library's stream) vs 8 TB/s
-  cpu_baseline  the CPU oracle timed on a bounded prefix of the same workload
-                (single thread), whose SAIF also re-checks the GPU result
+                launch time (HIP events on the library's stream) vs 8 TB/s,
+                with the measured HBM traffic and a copy kernel's bandwidth
+  cpu_baseline  the CPU oracle timed on bounded samples of the same workload:
+                one process per host core, and single-threaded (whose SAIF
+                also re-checks the GPU result)
   batched       64 uneven instances (1e4-5e5 gates, 200-5000 cycles) run as
                 one batch (autotuned, replayed from a captured HIP graph):
                 aggregate gate-cycles/s beside the same jobs run one by one,
                 with every instance's SAIF compared between the two
+  features      gate-eval rate with conditional arcs, with them averaged away
+                and with interconnect delays added (the paper's feature study)
   served        9 resident netlists, Poisson-arriving window and delay-edit
                 requests (200/s for 60 s): req/s, p50/p99 latency, served
                 gate-cycles/s, and a sample re-run alone and compared
@@ -277,6 +281,57 @@ def run_batch(args, torch, synth, G):
             "bit_exact_batch_vs_alone": bool(same), "oracle_sample_ok": bool(ok_oracle)}
 
 
+def averaged_arcs(arcs):
+    """The same arcs with every conditional pair replaced by one
+    unconditional record carrying the pair's mean rise and fall (the
+    "averaged SDF" variant of the paper's feature study, Table 7)."""
+    g, p, cp = arcs["gate"], arcs["pin"], arcs["cond_pin"]
+    unc = cp < 0
+    keys = {}
+    for i in np.nonzero(~unc)[0]:
+        keys.setdefault((int(g[i]), int(p[i])), []).append(i)
+    extra = sorted(keys.items())
+    out = {k: v[unc].copy() for k, v in arcs.items()}
+    add = {k: [] for k in arcs}
+    for (gg, pp), idx in extra:
+        add["gate"].append(gg)
+        add["pin"].append(pp)
+        add["cond_pin"].append(-1)
+        add["cond_val"].append(0)
+        add["rise"].append(int(round(float(np.mean(arcs["rise"][idx])))))
+        add["fall"].append(int(round(float(np.mean(arcs["fall"][idx])))))
+    return {k: np.concatenate([out[k], np.array(add[k], dtype=arcs[k].dtype)]) for k in arcs}
+
+
+def run_features(args, torch, synth, G):
+    """Cost of the timing features on the 1M-gate design (the paper's feature
+    study, Table 7): gate-eval time with conditional arcs (the benchmark's
+    arcs), with them averaged away, and with interconnect delays added."""
+    cycles = 2000
+    w = synth.scale(n_cycles=cycles)
+    net = w["netlist"]
+    variants = [("cond_arcs", w["arcs"], None), ("averaged_arcs", averaged_arcs(w["arcs"]), None),
+                ("cond_arcs_and_wires", w["arcs"], synth.make_wires(2, net, 1, 20))]
+    res = {}
+    for name, arcs, wires in variants:
+        sim = G.GateSim(device=0, stream=torch.cuda.current_stream(), window_cycles=cycles, timing=True)
+        d, s = sim.load_work(dict(w, arcs=arcs, wires=wires))
+        sim.simulate(d, s, 0, cycles)
+        sim.read_saif(d, reset=True)
+        sim.stats(reset=True)
+        for _ in range(2):
+            sim.simulate(d, s, 0, cycles)
+            sim.read_saif(d, reset=True)
+        st = sim.stats()
+        sim.close()
+        res[name] = round(2 * net["n_gates"] * cycles / (st["gate_eval_ms"] / 1e3), 1)
+        log(f"features: {name} {res[name]:.3g} gate-cycles/s (gate-eval time only)")
+    base = res["averaged_arcs"]
+    return {"workload": f"scale-1M, {cycles} cycles", "unit": "gate-cycles/s (gate-eval time)", **res,
+            "cond_overhead": round(base / res["cond_arcs"] - 1, 4),
+            "cond_and_wire_overhead": round(base / res["cond_arcs_and_wires"] - 1, 4)}
+
+
 def run_serve(args, torch, synth, G):
     import threading
     t_gen = time.time()
@@ -380,7 +435,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=["all", "scale", "batch", "serve"], default="all")
+    ap.add_argument("--mode", choices=["all", "scale", "batch", "features", "serve"], default="all")
     ap.add_argument("--cycles", type=int, default=10_000)
     ap.add_argument("--window", type=int, default=0, help="cycles per window (0 = the whole run, up to 16384)")
     ap.add_argument("--lds-cap", type=int, default=8)
@@ -412,10 +467,14 @@ def main():
         out.update(run_scale(args, torch, synth, G.GateSim))
     if args.mode in ("all", "batch"):
         out["batched"] = run_batch(args, torch, synth, G)
+    if args.mode in ("all", "features"):
+        out["features"] = run_features(args, torch, synth, G)
     if args.mode in ("all", "serve"):
         out["served"] = run_serve(args, torch, synth, G)
     if out["value"] is None:
         leg = out.get("batched") or out.get("served")
+        if leg is None:
+            leg = dict(out["features"], value=out["features"]["cond_arcs"], unit="gate-cycles/s")
         out["value"], out["unit"] = leg["value"], leg["unit"]
         out["config"] = {"workload": leg["workload"]}
     print(json.dumps(out), flush=True)
