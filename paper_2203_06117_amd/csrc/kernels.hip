@@ -642,6 +642,32 @@ __device__ __forceinline__ void walk(Cursor<K, WIRES, LDSRC> &P, const Arcs<K> &
     z_out = z;
 }
 
+// Interconnect filter (Algorithm 1, net-delay filtering) applied to one
+// lane's staged list of a pin, in place: walking the net's edges in order, an
+// edge followed by the next one sooner than the wire delay of the value it
+// goes to is dropped together with that next edge; every other edge becomes
+// a pin arrival at its time plus that delay.  v is the net's value before
+// the first edge.  On return [lo, hi) holds the arrivals.  Written without
+// branches: a lane writes behind its own read position only, and the word
+// read past its list (another lane's, or outside the stage) is never used.
+__device__ __forceinline__ void wire_filter_lds(uint32_t base, uint32_t lo, uint32_t &hi, uint32_t v, int32_t wr,
+                                                int32_t wf)
+{
+    uint32_t r = lo, o = lo;
+    while (r < hi) {
+        const int32_t e0 = gs_lds[base + r];
+        const int32_t e1 = gs_lds[base + r + 1];
+        const uint32_t nv = v ^ 1u;
+        const int32_t d = nv ? wr : wf;
+        const bool drop = r + 1 < hi && e1 - e0 < d;
+        gs_lds[base + o] = e0 + d;
+        o += drop ? 0u : 1u;
+        r += drop ? 2u : 1u;
+        v = drop ? v : nv;
+    }
+    hi = o;
+}
+
 // The event loop of `walk` for fanin words staged in LDS without
 // interconnect delays, written without branches: every pin's next word and
 // every state update is computed for all lanes and selected, so that a
@@ -872,18 +898,18 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
             int32_t cnt, acc = 0, z = 0;
             if (staged) {
-                Cursor<K, WIRES, true> P;
+                Cursor<K, false, true> P;
 #pragma unroll
                 for (int j = 0; j < K; j++) {
                     P.base[j] = base[j];
                     P.idx[j] = lo[j];
                     P.end[j] = hi[j];
+                    // with interconnect delays, each staged net list becomes
+                    // the pin's arrival list first
+                    if (WIRES) wire_filter_lds(base[j], lo[j], P.end[j], (state0 >> j) & 1u, arc.wr[j], arc.wf[j]);
                 }
                 P.state = state0;
-                if constexpr (!WIRES)
-                    walk_lds<K, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, cnt);
-                else
-                    walk<K, WIRES, true, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
+                walk_lds<K, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, cnt);
             } else {
                 Cursor<K, WIRES, false> P;
 #pragma unroll
@@ -947,7 +973,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     const int32_t ce = min(e, T);
                     s1 += v ? -ce : ce;
                 }
-                if (!staged || WIRES) s1 = acc;      // those walks kept their own sum
+                if (!staged) s1 = acc;                // that walk kept its own sum
                 acc = s1;
             }
             const uint64_t spill = __ballot(cnt > CAP);
