@@ -47,13 +47,22 @@ def _levels(n_inputs, n_gates, fanin_ptr, fanin_net):
     return lvl
 
 
-def _arc_delay(arcs_of_pin, state, rising):
-    cond = [a for a in arcs_of_pin if a[0] >= 0 and ((state >> a[0]) & 1) == a[1]]
-    unc = [a for a in arcs_of_pin if a[0] < 0]
-    pick = cond if cond else unc
+def _arc_delay(arcs_of_pin, pin, state, rising):
+    # records are (cond_pin, cond_val, in_edge, rise, fall); the pin's own bit
+    # in the post-switch state tells whether its input edge was a rise
+    in_rise = (state >> pin) & 1
+    ok = []
+    for cp, cv, ie, r, f in arcs_of_pin:
+        if cp >= 0 and ((state >> cp) & 1) != cv:
+            continue
+        if (ie == 1 and not in_rise) or (ie == 2 and in_rise):
+            continue
+        ok.append(((cp >= 0) + (ie != 0), r, f))
+    top = max((x[0] for x in ok), default=-1)
+    pick = [x for x in ok if x[0] == top]
     if len(pick) != 1:
         raise ValueError("arc records do not select exactly one delay")
-    return pick[0][2] if rising else pick[0][3]
+    return pick[0][1] if rising else pick[0][2]
 
 
 def _changes(samples):
@@ -107,7 +116,8 @@ def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, hor
     by_pin = {}
     for a in range(len(arcs["gate"])):
         key = (int(arcs["gate"][a]), int(arcs["pin"][a]))
-        by_pin.setdefault(key, []).append((int(arcs["cond_pin"][a]), int(arcs["cond_val"][a]),
+        ie = int(arcs["in_edge"][a]) if "in_edge" in arcs else 0
+        by_pin.setdefault(key, []).append((int(arcs["cond_pin"][a]), int(arcs["cond_val"][a]), ie,
                                            int(arcs["rise"][a]), int(arcs["fall"][a])))
     wr = [int(x) for x in wires["rise"]] if wires is not None else [0] * fp[-1]
     wf = [int(x) for x in wires["fall"]] if wires is not None else [0] * fp[-1]
@@ -143,7 +153,7 @@ def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, hor
                     continue
                 st = state(u + 1)
                 sw = [j for j in range(k) if pins[j][u + 1] != pins[j][u]]
-                d = min(_arc_delay(by_pin[(g, j)], st, y[u + 1] == 1) for j in sw)
+                d = min(_arc_delay(by_pin[(g, j)], j, st, y[u + 1] == 1) for j in sw)
                 sched.append(u + d)
             if sched and sched[-1] > H:
                 raise ValueError("horizon too short")

@@ -32,12 +32,18 @@
  *    evaluated once by truth-table lookup (pin 0 is the least significant
  *    bit of the table index).
  *
- *  - Gate delay (Algorithm 1, gate delay lookup; Section 3 on SDF): the
- *    delay of pin j's arc for output edge e in the gate's pin state s is the
- *    matching conditional record (its condition pin has the stated value in
- *    s) if there is one, else the unconditional record.  When several pins
- *    switch together the output edge takes the smallest of their delays,
- *    looked up in the state after all of them switched.
+ *  - Gate delay (Algorithm 1, gate delay lookup, whose delay rows are
+ *    indexed by the input edge and the output edge; Section 3 on SDF): the
+ *    delay of pin j's arc for output edge e in the gate's pin state s (after
+ *    the switch, so pin j's own bit gives its input edge: 1 = rising) comes
+ *    from the most specific matching record.  A record may carry a condition
+ *    (its condition pin has the stated value in s) and an input-edge
+ *    qualifier (rising or falling input only); each qualifier it carries
+ *    must hold, and its specificity is the number of qualifiers.  Exactly
+ *    one record of the highest matching specificity must exist for every
+ *    state.  When several pins switch together the output edge takes the
+ *    smallest of their delays, looked up in the state after all of them
+ *    switched.
  *
  *  - Gate inertial filter with PATHPULSEPERCENT = 100 (Algorithm 1, output
  *    filter; Section 3): after evaluation, with y the new value, z the value
@@ -113,14 +119,16 @@ void oracle_free(void *p)
 
 /*
  * Build a design.  Arc records follow the SDF reading above: cond_pin < 0
- * means unconditional.  wire_r / wire_f may be NULL (all zero).
+ * means unconditional; arc_in_edge (may be NULL: all 0) is 0 for either
+ * input edge, 1 for a rising, 2 for a falling input edge of the pin.
+ * wire_r / wire_f may be NULL (all zero).
  * Returns NULL and fills err on bad input.
  */
 void *oracle_new(int32_t n_inputs, int32_t n_gates,
                  int32_t n_cells, const uint8_t *cell_n_pins, const uint64_t *cell_truth,
                  const int32_t *cell_of_gate, const int64_t *fanin_ptr, const int32_t *fanin_net,
                  int64_t n_arcs, const int32_t *arc_gate, const int8_t *arc_pin,
-                 const int8_t *arc_cond_pin, const int8_t *arc_cond_val,
+                 const int8_t *arc_cond_pin, const int8_t *arc_cond_val, const int8_t *arc_in_edge,
                  const int32_t *arc_rise, const int32_t *arc_fall,
                  const int32_t *wire_rise, const int32_t *wire_fall,
                  char *err, int32_t errlen)
@@ -213,10 +221,10 @@ void *oracle_new(int32_t n_inputs, int32_t n_gates,
     }
 
     /* delay tables: for every fanin slot, every full pin state and both
-       output edges.  Unconditional records fill all states first; a
-       conditional record then overwrites the states where its condition pin
-       has its value.  Every entry must end up filled exactly once by the
-       winning kind of record. */
+       output edges.  Records are applied from the most specific kind (both
+       qualifiers) down to unqualified ones; a state takes the first kind
+       that matches it, and two records of that kind matching one state are
+       an error.  Every state must be matched. */
     {
         int64_t tot = 0;
         for (int64_t s = 0; s < F; s++) {
@@ -226,11 +234,13 @@ void *oracle_new(int32_t n_inputs, int32_t n_gates,
         d->dtab_ptr[F] = tot;
         d->dtab = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tot + 1));
         uint8_t *filled = (uint8_t *)calloc((size_t)tot + 1, 1);
-        for (int pass = 0; pass < 2; pass++) {
+        for (int pass = 2; pass >= 0; pass--) {
             for (int64_t a = 0; a < n_arcs; a++) {
                 int32_t g = arc_gate[a];
                 int is_cond = arc_cond_pin[a] >= 0;
-                if (is_cond != pass) continue;
+                int edge = arc_in_edge ? arc_in_edge[a] : 0;
+                if (edge < 0 || edge > 2) { set_err(err, errlen, "bad input-edge qualifier"); free(filled); oracle_free(d); return NULL; }
+                if (is_cond + (edge != 0) != pass) continue;
                 if (g < 0 || g >= G) { set_err(err, errlen, "arc gate out of range"); free(filled); oracle_free(d); return NULL; }
                 int32_t k = d->cell_pins[g], j = arc_pin[a];
                 if (j < 0 || j >= k) { set_err(err, errlen, "arc pin out of range"); free(filled); oracle_free(d); return NULL; }
@@ -240,6 +250,9 @@ void *oracle_new(int32_t n_inputs, int32_t n_gates,
                 int64_t base = d->dtab_ptr[fanin_ptr[g] + j];
                 for (int32_t st = 0; st < (1 << k); st++) {
                     if (is_cond && (((st >> q) & 1) != arc_cond_val[a])) continue;
+                    if (edge == 1 && !((st >> j) & 1)) continue;      /* rising input only */
+                    if (edge == 2 && ((st >> j) & 1)) continue;       /* falling input only */
+                    if (filled[base + 2 * st] > pass + 1) continue;   /* a more specific record holds it */
                     if (filled[base + 2 * st] == pass + 1) {
                         set_err(err, errlen, "two arc records match one pin state"); free(filled); oracle_free(d); return NULL;
                     }

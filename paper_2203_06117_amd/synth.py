@@ -217,13 +217,20 @@ def make_netlist(seed: int, n_gates: int, n_inputs: int, n_levels: int,
     }
 
 
-def make_arcs(seed: int, net: dict, lo: int, hi: int, cond_frac: float = 0.0) -> dict:
+def make_arcs(seed: int, net: dict, lo: int, hi: int, cond_frac: float = 0.0, edge_frac: float = 0.0) -> dict:
     """Per-(gate, pin) rise/fall delays, i.i.d. U{lo..hi} picoseconds.
 
     ``cond_frac`` of all gates (drawn among cells with at least two pins)
     carry SDF-style conditional delays: one pin's arc is replaced by two
     records keyed on one other pin of the same gate (value 0 and value 1),
     each with its own rise/fall pair.
+
+    ``edge_frac`` of all fanin slots get input-edge-qualified records
+    (``in_edge`` 1: rising input, 2: falling input), mixed three ways: an
+    unconditional slot either splits its record into a rising- and a
+    falling-input record, or keeps it and gains one record for one input
+    edge that overrides it there; a conditional slot gains one record with
+    both its condition (one value) and an input edge.
     """
     G = net["n_gates"]
     fp = net["fanin_ptr"]
@@ -273,7 +280,27 @@ def make_arcs(seed: int, net: dict, lo: int, hi: int, cond_frac: float = 0.0) ->
         cv[a:b] = val
         rise[a:b] = rr[cond_idx]
         fall[a:b] = ff[cond_idx]
-    return {"gate": gate, "pin": pin, "cond_pin": cp, "cond_val": cv, "rise": rise, "fall": fall}
+    in_edge = np.zeros(n_arcs, dtype=np.int8)
+    if edge_frac > 0:
+        e0 = 3_000_000_000_000
+        sel = s.unit(sl * 4 + e0) < edge_frac
+        split = (s.below(sl * 4 + 1 + e0, 2) == 0) & uncond
+        which = 1 + s.below(sl * 4 + 2 + e0, 2)
+        val = s.below(sl * 4 + 3 + e0, 2)
+        xr = lo + s.below(sl * 4 + 0 + 2 * e0, span)
+        xf = lo + s.below(sl * 4 + 1 + 2 * e0, span)
+        rec_of_slot = np.cumsum(uncond) - 1         # unconditional record of each unconditional slot
+        in_edge[rec_of_slot[sel & split]] = 1
+        add = np.nonzero(sel)[0]
+        gate = np.concatenate([gate, slot_gate[add].astype(np.int32)])
+        pin = np.concatenate([pin, slot_pin[add].astype(np.int8)])
+        cp = np.concatenate([cp, np.where(slot_is_cond[add], qpin[slot_gate[add]], -1).astype(np.int8)])
+        cv = np.concatenate([cv, np.where(slot_is_cond[add], val[add], 0).astype(np.int8)])
+        in_edge = np.concatenate([in_edge, np.where(split[add], 2, which[add]).astype(np.int8)])
+        rise = np.concatenate([rise, xr[add].astype(np.int32)])
+        fall = np.concatenate([fall, xf[add].astype(np.int32)])
+    return {"gate": gate, "pin": pin, "cond_pin": cp, "cond_val": cv, "in_edge": in_edge,
+            "rise": rise, "fall": fall}
 
 
 def make_wires(seed: int, net: dict, lo: int, hi: int) -> dict:
@@ -371,12 +398,12 @@ def glitchy(seed: int = 3, n_gates: int = 8_000_000, n_inputs: int = 150_000,
 def small_random(seed: int, n_gates: int, n_inputs: int, n_levels: int, n_cycles: int,
                  period: int, p: float, dlo: int, dhi: int, cond_frac: float = 0.0,
                  wire: tuple | None = None, extra: int = 0, extra_p: float = 0.0,
-                 skew: int = 50, wide: bool = False) -> dict:
+                 skew: int = 50, wide: bool = False, edge_frac: float = 0.0) -> dict:
     """Parametric small workload used by parity and property tests."""
     net = make_netlist(seed, n_gates, n_inputs, n_levels, wide=wide)
     wires = make_wires(seed, net, wire[0], wire[1]) if wire else None
     return {"name": f"rand-{seed}", "netlist": net,
-            "arcs": make_arcs(seed, net, dlo, dhi, cond_frac), "wires": wires,
+            "arcs": make_arcs(seed, net, dlo, dhi, cond_frac, edge_frac), "wires": wires,
             "stimulus": make_stimulus(seed, n_inputs, n_cycles, period, p, skew=skew,
                                       extra=extra, extra_p=extra_p)}
 

@@ -12,8 +12,8 @@ CELL = {name: i for i, name in enumerate(synth.WIDE_NAMES)}
 
 def work(n_inputs, gates, delays, toggles, init, period=1000, n_cycles=1, wires=None):
     """gates: list of (cell name, [fanin nets]); gate g drives net n_inputs + g.
-    delays: list of arc tuples (gate, pin, cond_pin, cond_val, rise, fall), or
-    a (rise, fall) pair applied unconditionally to every pin.
+    delays: list of arc tuples (gate, pin, cond_pin, cond_val, rise, fall
+    [, in_edge]), or a (rise, fall) pair applied unconditionally to every pin.
     toggles: per input, list of absolute toggle times.  wires: None or a list
     of (rise, fall) per fanin slot in CSR order."""
     cog = np.array([CELL[c] for c, _ in gates], dtype=np.int32)
@@ -30,6 +30,7 @@ def work(n_inputs, gates, delays, toggles, init, period=1000, n_cycles=1, wires=
         "cond_val": np.array([a[3] for a in delays], dtype=np.int8),
         "rise": np.array([a[4] for a in delays], dtype=np.int32),
         "fall": np.array([a[5] for a in delays], dtype=np.int32),
+        "in_edge": np.array([a[6] if len(a) > 6 else 0 for a in delays], dtype=np.int8),
     }
     tp = np.zeros(n_inputs + 1, dtype=np.int64)
     tp[1:] = np.cumsum([len(t) for t in toggles])

@@ -21,7 +21,7 @@ from oracle import brute
 from paper_2203_06117_amd import synth
 
 
-def _tiny(seed, wires, cond, zero, wide=False):
+def _tiny(seed, wires, cond, zero, wide=False, edges=False):
     rng = np.random.default_rng(seed)
     G = int(rng.integers(1, 11))
     I = int(rng.integers(3, 5)) + (3 if wide else 0)
@@ -30,15 +30,16 @@ def _tiny(seed, wires, cond, zero, wide=False):
     dlo, dhi = (0, 0) if zero else (1, int(rng.integers(1, 9)))
     w = synth.small_random(seed, G, I, L, 3, T, 0.5, dlo, dhi, cond_frac=0.5 if cond else 0.0,
                            wire=None if (zero or not wires) else (1, int(rng.integers(1, 7))),
-                           extra=2, extra_p=0.4, skew=T - 1, wide=wide)
+                           extra=2, extra_p=0.4, skew=T - 1, wide=wide, edge_frac=0.5 if edges else 0.0)
     return w
 
 
-@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "wide", "wide+wires+cond"])
+@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "wide", "wide+wires+cond",
+                                  "edges+cond", "wide+wires+cond+edges"])
 def test_oracle_matches_brute(mode):
     n_ok = 0
     for seed in range(1000, 1120):
-        w = _tiny(seed, "wires" in mode, "cond" in mode, mode == "zero", wide="wide" in mode)
+        w = _tiny(seed, "wires" in mode, "cond" in mode, mode == "zero", wide="wide" in mode, edges="edges" in mode)
         tc, t0, t1, waves = brute.simulate(w)
         N = len(tc)
         C = w["stimulus"]["n_cycles"]

@@ -212,6 +212,53 @@ def test_conditional_uses_state_after_switching():
     assert run1(w, [(2, 0)])["probes"][0][:2] == (1, [14])
 
 
+def test_input_edge_qualified_delays():
+    """SDF IOPATH rows qualified by the input edge (posedge / negedge A):
+    the delay row is picked by the input edge and the output edge
+    separately.  XOR2 makes all four combinations reachable from pin A.
+    Cycles: A rises with B=0, A falls with B=0, B rises, A rises with B=1,
+    A falls with B=1."""
+    ar, af, br, bf, rb, fb = 11, 13, 17, 19, 5, 7
+    arcs = [(0, 0, -1, 0, ar, af, 1), (0, 0, -1, 0, br, bf, 2), (0, 1, -1, 0, rb, fb)]
+    togA = [10, 110, 310, 410]
+    w = work(2, [("XOR2", [0, 1])], arcs, [togA, [210]], [0, 0], period=100, n_cycles=5)
+    got = [p[:2] for p in run1(w, [(2, c) for c in range(5)])["probes"]]
+    assert got == [(0, [10 + ar]),          # A rises, output rises
+                   (1, [10 + bf]),          # A falls, output falls
+                   (0, [10 + rb]),          # via B
+                   (1, [10 + af]),          # A rises, output falls
+                   (0, [10 + br])]          # A falls, output rises
+
+
+def test_specificity_order():
+    """A record qualified by both a condition and an input edge beats one
+    with a single qualifier, which beats an unqualified one; two records
+    of the top matching specificity are an error, and so is a pin state
+    that no record matches.  NAND2 pin 0, pin 1 held at 1, pin 0 rising
+    then falling: the output falls, then rises."""
+    base = [(0, 1, -1, 0, 50, 50)]
+    def run_arcs(a):
+        w = work(2, [("NAND2", [0, 1])], base + a, [[10, 110], []], [0, 1], period=100, n_cycles=2)
+        return [p[:2] for p in run1(w, [(2, 0), (2, 1)])["probes"]]
+    # unqualified only
+    assert run_arcs([(0, 0, -1, 0, 21, 23)]) == [(1, [33]), (0, [31])]
+    # a rising-input override beats it for the rising input only
+    assert run_arcs([(0, 0, -1, 0, 21, 23), (0, 0, -1, 0, 31, 3, 1)]) == [(1, [13]), (0, [31])]
+    # condition and edge together beat condition alone and edge alone
+    cond = [(0, 0, 1, 0, 40, 40), (0, 0, 1, 1, 21, 23)]
+    both = [(0, 0, 1, 0, 44, 44, 1), (0, 0, 1, 1, 61, 6, 1)]
+    assert run_arcs(cond + [(0, 0, -1, 0, 31, 3, 1)] + both) == [(1, [16]), (0, [31])]
+    # condition alone and edge alone both match pin 0 rising with pin 1 = 1
+    with pytest.raises(oracle.OracleError, match="two arc records"):
+        run_arcs(cond + [(0, 0, -1, 0, 31, 3, 1)])
+    # records dominated everywhere by more specific ones may repeat
+    assert run_arcs([(0, 0, -1, 0, 1, 1), (0, 0, -1, 0, 2, 2),
+                     (0, 0, -1, 0, 21, 23, 1), (0, 0, -1, 0, 27, 29, 2)]) == [(1, [33]), (0, [37])]
+    # nothing covers the falling input
+    with pytest.raises(oracle.OracleError, match="no arc record"):
+        run_arcs([(0, 0, -1, 0, 21, 23, 1)])
+
+
 def test_cycles_are_isolated():
     """Each cycle starts from the settled values; an edge later than the
     period still belongs to its cycle and is clipped out of T0/T1."""
