@@ -116,27 +116,34 @@ gs_status gs_load_cells(gs_ctx *ctx, int32_t n_cells, const uint8_t *n_pins, con
 gs_status gs_load_netlist(gs_ctx *ctx, int32_t n_inputs, int32_t n_gates, const int32_t *cell_of_gate,
                           const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t *design_id);
 
-/* One SDF-style delay arc (Algorithm 1's per-pin gate delay table, Section 3
- * on conditional delay statements): the delay from pin `pin` of `gate` to
- * the output for a rising (rise_ps) and a falling (fall_ps) output edge.
- * cond_pin < 0: unconditional.  cond_pin >= 0: applies only while pin
- * cond_pin of the same gate has value cond_val, and then takes precedence
- * over the unconditional record.  16 bytes, natural alignment. */
+/* One SDF-style delay arc (Algorithm 1's per-pin gate delay table, whose
+ * rows are indexed by input edge and output edge; Section 3 on conditional
+ * delay statements): the delay from pin `pin` of `gate` to the output for
+ * a rising (rise_ps) and a falling (fall_ps) output edge.  Two optional
+ * qualifiers restrict where a record applies:
+ *   cond_pin >= 0: only while pin cond_pin of the same gate has value
+ *                  cond_val (read after the switch); cond_pin < 0: always;
+ *   in_edge:       0 either input edge, 1 only when `pin` rises, 2 only when
+ *                  it falls (SDF posedge / negedge IOPATH rows).
+ * In each pin state the matching record with the most qualifiers wins.
+ * 16 bytes, natural alignment. */
 typedef struct {
     int32_t gate;
     int8_t  pin;
     int8_t  cond_pin;
     int8_t  cond_val;
-    int8_t  reserved;
+    int8_t  in_edge;
     int32_t rise_ps;
     int32_t fall_ps;
 } gs_arc;
 
-/* Delay arcs of a design.  For every (gate, pin, state of the other pins)
- * exactly one record must apply after precedence; all conditional records
- * of one (gate, pin) must key on the same condition pin.  Delays are either
- * all >= 1, or all 0 together with all wire delays (zero-delay mode).
- * Replaces earlier arcs of the design.  Errors: GS_E_INVALID. */
+/* Delay arcs of a design.  For every (gate, pin, pin state after the
+ * switch) exactly one record of the highest matching specificity must
+ * exist (records fully covered by more specific ones may repeat); all
+ * conditional records of one (gate, pin) must key on the same condition
+ * pin.  Delays are either all >= 1, or all 0 together with all wire delays
+ * (zero-delay mode).  Replaces earlier arcs of the design.
+ * Errors: GS_E_INVALID. */
 gs_status gs_load_arcs(gs_ctx *ctx, int32_t design, int64_t n_arcs, const gs_arc *arcs);
 
 /* Interconnect delays (Algorithm 1's per-pin wire delays), one rise/fall
@@ -265,9 +272,9 @@ gs_status gs_autotune(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_b
 typedef struct {
     int32_t gate;
     int8_t  pin;
-    int8_t  cond_pin;       /* selects the record being edited; -1 = unconditional */
+    int8_t  cond_pin;       /* with cond_val and in_edge, selects the record being edited */
     int8_t  cond_val;
-    int8_t  reserved;
+    int8_t  in_edge;
     int32_t rise_ps;        /* new delays */
     int32_t fall_ps;
 } gs_arc_edit;

@@ -86,22 +86,19 @@ extern "C" gs_status gs_check_netlist(int32_t n_cells, const uint8_t *n_pins, in
     return check_netlist_impl(nullptr, n_cells, n_pins, n_inputs, n_gates, cell_of_gate, fanin_ptr, fanin_net);
 }
 
-// Compiles arc records into one (q, r0, f0, r1, f1) record per fanin slot:
-// r/f 0 apply while pin q is 0, r/f 1 while it is 1.  Conditional records
-// take precedence over the unconditional one; every (gate, pin, side state)
-// must be covered by exactly one winning record.
+// Compiles arc records into one delay row per fanin slot (q, and 8 delays
+// in PinRec::d order): in each (condition value, input edge) combination
+// the most specific record applies, as arc_winner picks it.
 static gs_status compile_arcs(gs_ctx *ctx, const std::vector<uint8_t> &gate_k, const std::vector<int64_t> &fanin_ptr,
-                              int64_t n_arcs, const gs_arc *arcs, std::vector<int32_t> &q, std::vector<int32_t> &r0,
-                              std::vector<int32_t> &f0, std::vector<int32_t> &r1, std::vector<int32_t> &f1,
+                              int64_t n_arcs, const gs_arc *arcs, std::vector<int32_t> &q, std::vector<int32_t> &dl,
                               int32_t *max_delay, int32_t *zero_delay, std::vector<int64_t> *rec_out = nullptr)
 {
     const int32_t G = (int32_t)gate_k.size();
     const int64_t F = G ? fanin_ptr[G] : 0;
     if (n_arcs < 0 || (n_arcs > 0 && !arcs)) return gs_fail(ctx, GS_E_INVALID, "bad arc array");
-    // per slot: [0] unconditional record index, [1] cond val 0, [2] cond val 1
     std::vector<int64_t> local;
     std::vector<int64_t> &rec = rec_out ? *rec_out : local;
-    rec.assign(3 * (size_t)F, -1);
+    rec.assign(kArcKinds * (size_t)F, -1);
     q.assign(F, -1);
     int64_t n_zero = 0, n_pos = 0;
     int32_t mx = 0;
@@ -117,10 +114,9 @@ static gs_status compile_arcs(gs_ctx *ctx, const std::vector<uint8_t> &gate_k, c
         n_pos += (r.rise_ps > 0) + (r.fall_ps > 0);
         mx = std::max(mx, std::max(r.rise_ps, r.fall_ps));
         const int64_t s = fanin_ptr[r.gate] + r.pin;
-        int which;
-        if (r.cond_pin < 0) {
-            which = 0;
-        } else {
+        if (r.in_edge < 0 || r.in_edge > 2)
+            return gs_fail(ctx, GS_E_INVALID, "arc %lld: input-edge qualifier must be 0, 1 or 2", (long long)a);
+        if (r.cond_pin >= 0) {
             if (r.cond_pin >= k || r.cond_pin == r.pin)
                 return gs_fail(ctx, GS_E_INVALID, "arc %lld: bad condition pin %d", (long long)a, r.cond_pin);
             if (r.cond_val != 0 && r.cond_val != 1)
@@ -129,24 +125,27 @@ static gs_status compile_arcs(gs_ctx *ctx, const std::vector<uint8_t> &gate_k, c
                 return gs_fail(ctx, GS_E_INVALID, "gate %d pin %d: conditional arcs on more than one condition pin",
                                r.gate, r.pin);
             q[s] = r.cond_pin;
-            which = 1 + r.cond_val;
         }
-        if (rec[3 * s + which] >= 0)
-            return gs_fail(ctx, GS_E_INVALID, "gate %d pin %d: two arc records apply to one pin state", r.gate, r.pin);
-        rec[3 * s + which] = a;
+        int64_t &slot = rec[kArcKinds * s + arc_kind(r)];
+        slot = slot == -1 ? a : -2;
     }
     if (n_zero > 0 && n_pos > 0)
         return gs_fail(ctx, GS_E_INVALID, "gate delays must be all >= 1, or all 0 (zero-delay mode)");
-    r0.assign(F, 0); f0.assign(F, 0); r1.assign(F, 0); f1.assign(F, 0);
+    dl.assign(8 * (size_t)F, 0);
     for (int32_t g = 0; g < G; g++)
         for (int64_t s = fanin_ptr[g]; s < fanin_ptr[g + 1]; s++) {
-            int64_t u = rec[3 * s], c0 = rec[3 * s + 1], c1 = rec[3 * s + 2];
-            int64_t a0 = c0 >= 0 ? c0 : u, a1 = c1 >= 0 ? c1 : u;
-            if (a0 < 0 || a1 < 0)
-                return gs_fail(ctx, GS_E_INVALID, "gate %d pin %lld: a pin state has no arc record", g,
-                               (long long)(s - fanin_ptr[g]));
-            r0[s] = arcs[a0].rise_ps; f0[s] = arcs[a0].fall_ps;
-            r1[s] = arcs[a1].rise_ps; f1[s] = arcs[a1].fall_ps;
+            for (int cv = 0; cv < 2; cv++)
+                for (int ie = 0; ie < 2; ie++) {
+                    const int64_t w = arc_winner(&rec[kArcKinds * s], cv, ie);
+                    if (w == -1)
+                        return gs_fail(ctx, GS_E_INVALID, "gate %d pin %lld: a pin state has no arc record", g,
+                                       (long long)(s - fanin_ptr[g]));
+                    if (w == -2)
+                        return gs_fail(ctx, GS_E_INVALID, "gate %d pin %lld: two arc records apply to one pin state",
+                                       g, (long long)(s - fanin_ptr[g]));
+                    dl[8 * s + gs::delay_slot(cv, ie, 1)] = arcs[w].rise_ps;
+                    dl[8 * s + gs::delay_slot(cv, ie, 0)] = arcs[w].fall_ps;
+                }
             if (q[s] < 0) q[s] = 0;
         }
     *max_delay = mx;
@@ -166,9 +165,9 @@ extern "C" gs_status gs_check_arcs(int32_t n_cells, const uint8_t *n_pins, int32
         k[g] = n_pins[cell_of_gate[g]];
         fp[g + 1] = fp[g] + k[g];
     }
-    std::vector<int32_t> q, r0, f0, r1, f1;
+    std::vector<int32_t> q, dl;
     int32_t mx, zd;
-    return compile_arcs(nullptr, k, fp, n_arcs, arcs, q, r0, f0, r1, f1, &mx, &zd);
+    return compile_arcs(nullptr, k, fp, n_arcs, arcs, q, dl, &mx, &zd);
 }
 
 static gs_status check_stim_impl(gs_ctx *ctx, int32_t n_inputs, int32_t period, int32_t n_cycles, const uint8_t *init,
@@ -480,7 +479,7 @@ static gs_status pack_design(gs_ctx *ctx, Design *d)
             PinRec &q = pins[pc++];
             q.net = d->fanin_net[s];
             q.q = d->q[s];
-            q.r0 = d->r0[s]; q.f0 = d->f0[s]; q.r1 = d->r1[s]; q.f1 = d->f1[s];
+            for (int i = 0; i < 8; i++) q.d[i] = d->dl[8 * s + i];
             q.wr = d->wr[s]; q.wf = d->wf[s];
         }
     }
@@ -504,13 +503,13 @@ extern "C" gs_status gs_load_arcs(gs_ctx *ctx, int32_t design, int64_t n_arcs, c
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
     Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
-    std::vector<int32_t> q, r0, f0, r1, f1;
+    std::vector<int32_t> q, dl;
     std::vector<int64_t> rec;
     int32_t mx, zd;
-    gs_status st = compile_arcs(ctx, d->gate_k, d->fanin_ptr, n_arcs, arcs, q, r0, f0, r1, f1, &mx, &zd, &rec);
+    gs_status st = compile_arcs(ctx, d->gate_k, d->fanin_ptr, n_arcs, arcs, q, dl, &mx, &zd, &rec);
     if (st) return st;
     if (zd && d->has_wires) return gs_fail(ctx, GS_E_INVALID, "zero-delay arcs need zero wire delays");
-    d->q.swap(q); d->r0.swap(r0); d->f0.swap(f0); d->r1.swap(r1); d->f1.swap(f1);
+    d->q.swap(q); d->dl.swap(dl);
     d->slot_rec.swap(rec);
     d->arcs.assign(arcs, arcs + n_arcs);
     d->max_delay = mx;

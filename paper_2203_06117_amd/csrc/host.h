@@ -14,6 +14,33 @@
 #include <thread>
 #include <vector>
 
+// Arc records of one fanin slot sorted by kind: kind = 3 * c + e with c = 0
+// for an unconditional record, else 1 + its condition value, and e its
+// input-edge qualifier (0 either edge, 1 rising, 2 falling).  Each entry is
+// the record's index, -1 for none or -2 for more than one.
+constexpr int kArcKinds = 9;
+
+template <class R> inline int arc_kind(const R &a)
+{
+    return 3 * (a.cond_pin < 0 ? 0 : 1 + (a.cond_val ? 1 : 0)) + a.in_edge;
+}
+
+// The record that sets a slot's delays where its condition pin has value cv
+// and its input edge is ie (1 rising): the most specific kind that applies
+// (condition and edge; then condition alone or edge alone, which must not
+// both exist; then neither).  -1: no record applies; -2: not unique.
+inline int64_t arc_winner(const int64_t *kind, int cv, int ie)
+{
+    const int e = ie ? 1 : 2;
+    const int64_t both = kind[3 * (1 + cv) + e];
+    if (both != -1) return both;
+    const int64_t c = kind[3 * (1 + cv)], x = kind[e];
+    if (c != -1 && x != -1) return -2;
+    if (c != -1) return c;
+    if (x != -1) return x;
+    return kind[0];
+}
+
 struct Design {
     int32_t I = 0, G = 0, N = 0, L = 0;
     int64_t F = 0;
@@ -28,8 +55,8 @@ struct Design {
     std::vector<int32_t> level_kmax;     // largest pin count in each level
     int32_t level_sweeps = 0;
     // compiled delays per fanin slot
-    std::vector<int32_t> q, r0, f0, r1, f1, wr, wf;
-    std::vector<int64_t> slot_rec;       // per fanin slot: arc record of [uncond, cond=0, cond=1], -1 if none
+    std::vector<int32_t> q, dl, wr, wf;  // dl: 8 per slot, PinRec::d order
+    std::vector<int64_t> slot_rec;       // kArcKinds per slot, as arc_winner reads them
     std::vector<gs_arc> arcs;            // the loaded arc records
     bool arcs_loaded = false, has_wires = false;
     int32_t zero_delay = 0, max_delay = 0, max_wire = 0;

@@ -26,13 +26,17 @@ struct GateRec {
     uint64_t pad2;
 };
 
-// One gate pin (fanin arc), 32 bytes.  The delay of this pin's arc for an
-// output edge is r/f "0" while pin q of the gate is 0 and r/f "1" while it
-// is 1 (an unconditional arc has r0 == r1 and f0 == f1).
+// Index into a pin's delay row: cv = value of the row's condition pin q,
+// ie = 1 for a rising input edge, oe = 1 for a rising output edge, all read
+// in the gate's pin state after the switch (ie is the pin's own bit there).
+__host__ __device__ constexpr int delay_slot(int cv, int ie, int oe) { return (cv << 2) | (ie << 1) | oe; }
+
+// One gate pin (fanin arc), 48 bytes: its net, the condition pin q of its
+// delay row, the row d[delay_slot(cv, ie, oe)] and its interconnect delays.
 struct PinRec {
     int32_t net;
     int32_t q;
-    int32_t r0, f0, r1, f1;
+    int32_t d[8];
     int32_t wr, wf;     // interconnect rise / fall delay
 };
 
@@ -140,7 +144,7 @@ hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
 struct EditRec {
     uint32_t out;
     uint32_t pin;
-    int32_t r0, f0, r1, f1;
+    int32_t d[8];       // the new delay row, as PinRec::d
 };
 
 // Fanout-cone marking for delay edits, one launch per level: mark[out] |= the

@@ -484,26 +484,35 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l)
 // Arc data of one gate's pins (wave-uniform).
 template <int K>
 struct Arcs {
-    int32_t q[K], r0[K], f0[K], r1[K], f1[K], wr[K], wf[K];
+    int32_t q[K], d[K][8], wr[K], wf[K];
+
+    // Pin j's arc delay for output value y in pin state st (after the
+    // switch).  Arithmetic selects: a select between array elements would
+    // become an address select and force the arrays to scratch.
+    __device__ __forceinline__ int32_t pin_delay(int j, uint32_t st, int y) const
+    {
+        const int32_t mc = -(int32_t)((st >> q[j]) & 1), me = -(int32_t)((st >> j) & 1), mo = -(int32_t)y;
+        int32_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[i] = d[j][i] + (mc & (d[j][i + 4] - d[j][i]));   // condition value
+        const int32_t f = v[0] + (me & (v[2] - v[0]));                                   // input edge
+        const int32_t r = v[1] + (me & (v[3] - v[1]));
+        return f + (mo & (r - f));                                                       // output edge
+    }
 
     // Smallest arc delay over the pins in sw for output value y, in pin
     // state st (gates with more than three pins; smaller gates read it from
     // the wave's lookup table).
     __device__ __forceinline__ int32_t delay(uint32_t st, uint32_t sw, int y) const
     {
-        int32_t d = kInf;
+        int32_t dm = kInf;
 #pragma unroll
         for (int j = 0; j < K; j++) {
-            // arithmetic selects: a select between array elements would
-            // become an address select and force the arrays to scratch
-            const int32_t sel = -(int32_t)((st >> q[j]) & 1);
-            const int32_t rise = r0[j] + (sel & (r1[j] - r0[j]));
-            const int32_t fall = f0[j] + (sel & (f1[j] - f0[j]));
-            const int32_t dj = fall + ((-y) & (rise - fall));
+            const int32_t dj = pin_delay(j, st, y);
             const int32_t m = -(int32_t)((sw >> j) & 1);
-            d = min(d, (dj & m) | (kInf & ~m));
+            dm = min(dm, (dj & m) | (kInf & ~m));
         }
-        return d;
+        return dm;
     }
 };
 
@@ -568,10 +577,7 @@ __device__ __forceinline__ void build_lut(const Arcs<K> &arc, uint64_t truth, in
     int32_t d = kInf >> 1;
 #pragma unroll
     for (int j = 0; j < K; j++) {
-        const int32_t sel = -(int32_t)((st >> arc.q[j]) & 1);
-        const int32_t rise = arc.r0[j] + (sel & (arc.r1[j] - arc.r0[j]));
-        const int32_t fall = arc.f0[j] + (sel & (arc.f1[j] - arc.f0[j]));
-        const int32_t dj = fall + ((-y) & (rise - fall));
+        const int32_t dj = arc.pin_delay(j, st, y);
         const int32_t mj = -(int32_t)((m >> j) & 1);
         d = min(d, (dj & mj) | ((kInf >> 1) & ~mj));
     }
@@ -761,7 +767,9 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             resident[j] = sl < 0;
             row[j] = sl < 0 ? (uint32_t)pr.net : (uint32_t)sl;
         }
-        arc.q[j] = pr.q; arc.r0[j] = pr.r0; arc.f0[j] = pr.f0; arc.r1[j] = pr.r1; arc.f1[j] = pr.f1;
+        arc.q[j] = pr.q;
+#pragma unroll
+        for (int i = 0; i < 8; i++) arc.d[j][i] = pr.d[i];
         arc.wr[j] = pr.wr; arc.wf[j] = pr.wf;
     }
     if (K <= 3) {
@@ -1224,10 +1232,8 @@ __global__ void edit_apply_kernel(const EditRec *__restrict__ ed, uint32_t n, co
     const int32_t sl = slot[e.out];
     if (sl < 0 || (uint32_t)sl >= n_cone || e.pin >= stride) return;
     PinRec &r = cp[(uint32_t)sl * stride + e.pin];
-    r.r0 = e.r0;
-    r.f0 = e.f0;
-    r.r1 = e.r1;
-    r.f1 = e.f1;
+#pragma unroll
+    for (int i = 0; i < 8; i++) r.d[i] = e.d[i];
 }
 
 hipError_t launch_edit_apply(const EditRec *ed, uint32_t n, const int32_t *slot, PinRec *cp, uint32_t stride,

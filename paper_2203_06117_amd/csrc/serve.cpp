@@ -327,8 +327,15 @@ gs_status admit(gs_ctx *ctx, ServeState *S, Req &q, bool &fits, std::string &err
             return GS_E_INVALID;
         }
         const int64_t sl = d->fanin_ptr[e.gate] + e.pin;
-        const int which = e.cond_pin < 0 ? 0 : 1 + (e.cond_val ? 1 : 0);
-        const int64_t a = d->slot_rec[3 * sl + which];
+        if (e.in_edge < 0 || e.in_edge > 2) {
+            err = "edit has a bad input-edge qualifier";
+            return GS_E_INVALID;
+        }
+        const int64_t a = d->slot_rec[kArcKinds * sl + arc_kind(e)];
+        if (a == -2) {
+            err = "edit names more than one arc record";
+            return GS_E_INVALID;
+        }
         if (a < 0 || (e.cond_pin >= 0 && d->arcs[a].cond_pin != e.cond_pin)) {
             err = "edit names an arc record that does not exist";
             return GS_E_INVALID;
@@ -351,8 +358,6 @@ gs_status admit(gs_ctx *ctx, ServeState *S, Req &q, bool &fits, std::string &err
     for (auto &kv : slots) {
         const int64_t sl = kv.first;
         const int32_t g = kv.second;
-        const int64_t u = d->slot_rec[3 * sl], a0 = d->slot_rec[3 * sl + 1] >= 0 ? d->slot_rec[3 * sl + 1] : u,
-                      a1 = d->slot_rec[3 * sl + 2] >= 0 ? d->slot_rec[3 * sl + 2] : u;
         auto del = [&](int64_t a, int rise) -> int32_t {
             auto it = newdel.find(a);
             if (it != newdel.end()) return it->second[rise ? 0 : 1];
@@ -361,7 +366,13 @@ gs_status admit(gs_ctx *ctx, ServeState *S, Req &q, bool &fits, std::string &err
         EditRec e;
         e.out = (uint32_t)(d->I + g);
         e.pin = (uint32_t)(sl - d->fanin_ptr[g]);
-        e.r0 = del(a0, 1); e.f0 = del(a0, 0); e.r1 = del(a1, 1); e.f1 = del(a1, 0);
+        for (int cv = 0; cv < 2; cv++)
+            for (int ie = 0; ie < 2; ie++) {
+                // the load resolved every combination, so a unique winner exists
+                const int64_t w = arc_winner(&d->slot_rec[kArcKinds * sl], cv, ie);
+                e.d[gs::delay_slot(cv, ie, 1)] = del(w, 1);
+                e.d[gs::delay_slot(cv, ie, 0)] = del(w, 0);
+            }
         er.push_back(e);
         if (enets.empty() || enets.back() != e.out) enets.push_back(e.out);
     }

@@ -34,7 +34,7 @@ SCHED_LEVELS, SCHED_GRAPH = 0, 1
 REQ_WINDOW, REQ_EDIT = 0, 1
 
 ARC_DTYPE = np.dtype([("gate", "<i4"), ("pin", "i1"), ("cond_pin", "i1"), ("cond_val", "i1"),
-                      ("reserved", "i1"), ("rise", "<i4"), ("fall", "<i4")])
+                      ("in_edge", "i1"), ("rise", "<i4"), ("fall", "<i4")])
 assert ARC_DTYPE.itemsize == 16
 
 
@@ -70,7 +70,7 @@ class Job(C.Structure):
 
 class ArcEdit(C.Structure):
     _fields_ = [("gate", C.c_int32), ("pin", C.c_int8), ("cond_pin", C.c_int8), ("cond_val", C.c_int8),
-                ("reserved", C.c_int8), ("rise_ps", C.c_int32), ("fall_ps", C.c_int32)]
+                ("in_edge", C.c_int8), ("rise_ps", C.c_int32), ("fall_ps", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -158,13 +158,14 @@ def last_error() -> str:
 
 
 def arcs_array(arcs) -> np.ndarray:
-    """SoA dict (gate, pin, cond_pin, cond_val, rise, fall) -> gs_arc records."""
+    """SoA dict (gate, pin, cond_pin, cond_val, rise, fall[, in_edge]) -> gs_arc records."""
     if isinstance(arcs, np.ndarray) and arcs.dtype == ARC_DTYPE:
         return np.ascontiguousarray(arcs)
     n = len(arcs["gate"])
     a = np.zeros(n, dtype=ARC_DTYPE)
     for k in ("gate", "pin", "cond_pin", "cond_val", "rise", "fall"):
         a[k] = arcs[k]
+    a["in_edge"] = arcs["in_edge"] if "in_edge" in arcs else 0
     return a
 
 
@@ -344,8 +345,9 @@ class GateSim:
         return t.value
 
     def submit_edit(self, design, stim, edits) -> int:
-        """edits: list of (gate, pin, cond_pin, cond_val, rise, fall)."""
-        arr = (ArcEdit * max(1, len(edits)))(*[ArcEdit(e[0], e[1], e[2], e[3], 0, e[4], e[5]) for e in edits])
+        """edits: list of (gate, pin, cond_pin, cond_val, rise, fall[, in_edge])."""
+        arr = (ArcEdit * max(1, len(edits)))(*[ArcEdit(e[0], e[1], e[2], e[3], e[6] if len(e) > 6 else 0, e[4], e[5])
+                                               for e in edits])
         r = Request(REQ_EDIT, design, stim, 0, 0, len(edits), arr)
         t = C.c_uint64()
         self._chk(_lib.gs_submit(self._h, C.byref(r), C.byref(t)))

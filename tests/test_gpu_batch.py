@@ -45,7 +45,7 @@ def uneven_jobs(n, seed0=400, gmax=3000, wide_every=0):
         wide = wide_every > 0 and i % wide_every == 1
         inputs = max(inputs, 8) if wide else inputs
         works.append(synth.small_random(seed0 + i, g, inputs, min(levels, g), cycles, 800, p, 5, 80, cond_frac=0.1,
-                                        wide=wide))
+                                        wide=wide, edge_frac=0.3 if i % 3 == 2 else 0.0))
     return works
 
 

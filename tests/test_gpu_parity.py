@@ -93,7 +93,7 @@ def test_pulse_grid(G, cell):
     assert_same(w, got, oracle.simulate(w), cell)
 
 
-@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "multi-edge"])
+@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "multi-edge", "wires+cond+edges"])
 def test_random_small(G, mode):
     for seed in range(20):
         rng = np.random.default_rng(seed + 100)
@@ -107,7 +107,7 @@ def test_random_small(G, mode):
                                cond_frac=0.3 if "cond" in mode else 0.0,
                                wire=(1, int(rng.integers(1, 25))) if "wires" in mode else None,
                                extra=3 if mode in ("multi-edge", "wires") else 0, extra_p=0.3,
-                               skew=min(50, T - 1))
+                               skew=min(50, T - 1), edge_frac=0.4 if "edges" in mode else 0.0)
         say("random", mode, seed, gates, levels, C, T)
         got = gpu_saif(G, w, window_cycles=int(rng.choice([0, 64, 100, 37])))
         assert_same(w, got, oracle.simulate(w), f"{mode} seed {seed}")
@@ -148,7 +148,8 @@ def test_dense_activity(G):
     """Inputs with about six toggles per cycle: tile groups carry more fanin
     words than the on-chip stage holds, so waves walk the arena directly, and
     output lists outgrow the LDS staging; both paths must match the oracle."""
-    w = synth.small_random(77, 600, 16, 12, 200, 2000, 0.9, 2, 60, cond_frac=0.2, extra=6, extra_p=0.9)
+    w = synth.small_random(77, 600, 16, 12, 200, 2000, 0.9, 2, 60, cond_frac=0.2, extra=6, extra_p=0.9,
+                           edge_frac=0.3)
     for opt in (dict(), dict(tiles_per_wave=2, lds_cap=4)):
         say("dense", opt)
         got = gpu_saif(G, w, **opt)
@@ -161,10 +162,11 @@ def test_dense_activity(G):
 def test_wide_cells(G, opt):
     """Cells of four to six pins (no delay lookup table; arc delays chosen per
     event, two tiles per staging group) mixed with the base cells, with
-    conditional arcs and glitchy inputs, with and without wire delays."""
+    conditional arcs and glitchy inputs, with and without wire delays (with
+    wires also with input-edge-qualified arcs)."""
     for wire in (None, (1, 6)):
         w = synth.small_random(91, 1500, 40, 20, 200, 600, 0.3, 2, 60, cond_frac=0.2, extra=2, extra_p=0.3,
-                               wide=True, wire=wire)
+                               wide=True, wire=wire, edge_frac=0.3 if wire else 0.0)
         say("wide", opt, wire)
         rng = np.random.default_rng(5)
         N = 40 + 1500

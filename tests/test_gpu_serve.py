@@ -36,8 +36,8 @@ def same(got, ref, tag):
 
 def edited_arcs(arcs, edits):
     a = {k: v.copy() for k, v in arcs.items()}
-    for g, p, cp, cv, r, f in edits:
-        m = (a["gate"] == g) & (a["pin"] == p) & (a["cond_pin"] == cp)
+    for g, p, cp, cv, r, f, ie in edits:
+        m = (a["gate"] == g) & (a["pin"] == p) & (a["cond_pin"] == cp) & (a["in_edge"] == ie)
         if cp >= 0:
             m &= a["cond_val"] == cv
         assert m.sum() == 1
@@ -53,14 +53,16 @@ def random_edits(rng, w, n):
     for i in idx:
         r = max(1, int(round(arcs["rise"][i] * (1 + rng.uniform(-0.2, 0.2)))))
         f = max(1, int(round(arcs["fall"][i] * (1 + rng.uniform(-0.2, 0.2)))))
-        out.append((int(arcs["gate"][i]), int(arcs["pin"][i]), int(arcs["cond_pin"][i]), int(arcs["cond_val"][i]), r, f))
+        out.append((int(arcs["gate"][i]), int(arcs["pin"][i]), int(arcs["cond_pin"][i]), int(arcs["cond_val"][i]), r, f,
+                    int(arcs["in_edge"][i])))
     return out
 
 
 @pytest.fixture(scope="module")
 def served(G):
-    # the third design also has four- to six-pin cells
-    works = [synth.small_random(600 + i, g, max(8, g // 50), lv, 400, 800, 0.2, 5, 80, cond_frac=0.1, wide=i == 2)
+    # the second design has input-edge-qualified arcs, the third four- to six-pin cells and both
+    works = [synth.small_random(600 + i, g, max(8, g // 50), lv, 400, 800, 0.2, 5, 80, cond_frac=0.1, wide=i == 2,
+                                edge_frac=0.3 if i else 0.0)
              for i, (g, lv) in enumerate(((3000, 30), (1200, 20), (600, 12)))]
     sim = G.GateSim()
     sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)
@@ -152,6 +154,11 @@ def test_bad_edit_is_rejected(served):
     a = works[0]["arcs"]
     i = int(np.nonzero(a["cond_pin"] < 0)[0][0])
     t = sim.submit_edit(*ids[0], [(int(a["gate"][i]), int(a["pin"][i]), 0 if a["pin"][i] else 1, 1, 5, 5)])
+    r = sim.poll(t, wait=True)
+    sim.release(t)
+    assert r["status"] != 0
+    # the first design has no input-edge-qualified records to edit
+    t = sim.submit_edit(*ids[0], [(int(a["gate"][i]), int(a["pin"][i]), -1, 0, 5, 5, 1)])
     r = sim.poll(t, wait=True)
     sim.release(t)
     assert r["status"] != 0

@@ -74,6 +74,38 @@ def test_check_arcs():
     assert G.check_arcs(h["netlist"]["cell_pins"], h["netlist"]["cell_of_gate"], h["arcs"]) == G.GS_E_INVALID
 
 
+def test_check_arcs_agrees_with_oracle_on_qualified_records():
+    """Random mixes of condition- and input-edge-qualified records on one
+    pin (some kinds repeated): the library accepts exactly the sets the
+    oracle accepts (one record of the top matching specificity per pin
+    state; dominated repeats allowed)."""
+    import oracle
+    rng = np.random.default_rng(5)
+    kinds = [(c, e) for c in (-1, 0, 1) for e in (0, 1, 2)]
+    n_ok = n_bad = 0
+    for trial in range(400):
+        recs = [(0, 1, -1, 0, 9, 9)]                     # pin 1 always covered
+        for (c, e) in kinds:
+            m = rng.choice([0, 0, 1, 1, 2])
+            for _ in range(m):
+                recs.append((0, 0, 1 if c >= 0 else -1, max(c, 0), int(rng.integers(1, 50)),
+                             int(rng.integers(1, 50)), e))
+        h = work(2, [("XOR2", [0, 1])], recs, [[], []], [0, 0])
+        lib_ok = G.check_arcs(h["netlist"]["cell_pins"], h["netlist"]["cell_of_gate"], h["arcs"]) == G.GS_OK
+        try:
+            oracle.Oracle(h["netlist"], h["arcs"])
+            or_ok = True
+        except oracle.OracleError:
+            or_ok = False
+        assert lib_ok == or_ok, recs
+        n_ok += lib_ok
+        n_bad += not lib_ok
+    assert n_ok > 20 and n_bad > 20
+    # a qualifier outside 0..2 is rejected
+    h = work(1, [("BUF", [0])], [(0, 0, -1, 0, 3, 4, 3)], [[]], [0])
+    assert G.check_arcs(h["netlist"]["cell_pins"], h["netlist"]["cell_of_gate"], h["arcs"]) == G.GS_E_INVALID
+
+
 def test_check_stimulus():
     s = synth.make_stimulus(4, 10, 50, 100, 0.4, skew=20, extra=2, extra_p=0.3)
     args = (10, 100, 50, s["init"], s["toggle_ptr"], s["toggle_ps"])
