@@ -112,15 +112,29 @@ class Oracle:
         return _load().oracle_level(self._h, int(net))
 
     def run(self, stim: dict, cycle_begin: int = 0, cycle_end: int | None = None,
-            probes=None, probe_cap: int = 4096):
+            probes=None, probe_cap: int = 4096, segment_cycles: int = 1):
         """Simulate cycles [cycle_begin, cycle_end).
 
         Returns a dict with int64 arrays tc, t0, t1 and ig (glitch toggles; one
         entry per net: inputs first, then gate g's output as net n_inputs + g),
         event and edge counts, and — for each (net, cycle) probe — (initial
         value, [times]).
+
+        segment_cycles S > 1: each group of S consecutive cycles (from cycle
+        0; n_cycles must be a multiple of S) is one continuous run from the
+        settled state at its start, so edges and pending events cross the
+        cycle boundaries inside it (Section 1's re-simulation without the
+        per-cycle isolation).  The simulator is then given the group as its
+        interval: cycle_begin / cycle_end and probe cycles count groups,
+        probe times are local to the group, T0 / T1 cover the group, and ig
+        counts each group's edges beyond its net value change.
         """
         lib = _load()
+        S = int(segment_cycles)
+        if S < 1 or int(stim["n_cycles"]) % S:
+            raise OracleError("n_cycles must be a multiple of segment_cycles")
+        if S > 1:
+            stim = dict(stim, period=int(stim["period"]) * S, n_cycles=int(stim["n_cycles"]) // S)
         if cycle_end is None:
             cycle_end = int(stim["n_cycles"])
         N = self.n_inputs + self.n_gates
@@ -153,7 +167,8 @@ class Oracle:
                 "probes": out}
 
 
-def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, probes=None):
+def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, probes=None,
+             segment_cycles: int = 1):
     """Convenience: load ``work`` (a synth workload dict) and run it."""
     o = Oracle(work["netlist"], work["arcs"], work.get("wires"))
-    return o.run(work["stimulus"], cycle_begin, cycle_end, probes)
+    return o.run(work["stimulus"], cycle_begin, cycle_end, probes, segment_cycles=segment_cycles)

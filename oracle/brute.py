@@ -98,12 +98,20 @@ def _wire(net_samples, dr, df, H):
     return _samples(v0, out, H)
 
 
-def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, horizon: int | None = None):
-    """Returns (tc, t0, t1, waves) with waves[(net, cycle)] = (init, [times])."""
+def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, horizon: int | None = None,
+             segment_cycles: int = 1):
+    """Returns (tc, t0, t1, waves) with waves[(net, cycle)] = (init, [times]).
+
+    segment_cycles S: every S cycles form one interval simulated from its
+    settled start (cycles and times in the results then count intervals)."""
     net = work["netlist"]
     arcs = work["arcs"]
     wires = work.get("wires")
     stim = work["stimulus"]
+    if segment_cycles > 1:
+        assert int(stim["n_cycles"]) % segment_cycles == 0
+        stim = dict(stim, period=int(stim["period"]) * segment_cycles,
+                    n_cycles=int(stim["n_cycles"]) // segment_cycles)
     I, G = int(net["n_inputs"]), int(net["n_gates"])
     fp = [int(x) for x in net["fanin_ptr"]]
     fn = [int(x) for x in net["fanin_net"]]

@@ -259,6 +259,28 @@ def test_specificity_order():
         run_arcs([(0, 0, -1, 0, 21, 23, 1)])
 
 
+def test_continuous_segments():
+    """Two cycles run as one segment: a BUF slower than the period lets
+    its edge carry into the next cycle, where the input's return swallows
+    it (t < W cancels the pending edge); run cycle by cycle, each cycle
+    shows the edge instead.  A lone input edge: the output spends only the
+    segment's last 30 ps at 1."""
+    w = work(1, [("BUF", [0])], (150, 150), [[20, 120]], [0], period=100, n_cycles=2)
+    iso = run1(w, [(1, 0), (1, 1)])
+    assert [p[:2] for p in iso["probes"]] == [(0, [170]), (1, [170])]
+    assert iso["tc"].tolist() == [2, 2] and iso["t1"].tolist() == [100, 100]
+    seg = oracle.simulate(w, probes=[(1, 0), (0, 0)], segment_cycles=2)
+    assert [p[:2] for p in seg["probes"]] == [(0, []), (0, [20, 120])]
+    assert seg["tc"].tolist() == [2, 0] and seg["t1"].tolist() == [100, 0] and seg["t0"].tolist() == [100, 200]
+    w = work(1, [("BUF", [0])], (150, 150), [[20]], [0], period=100, n_cycles=2)
+    seg = oracle.simulate(w, probes=[(1, 0)], segment_cycles=2)
+    assert seg["probes"][0][:2] == (0, [170])
+    assert seg["tc"].tolist() == [1, 1] and seg["t1"].tolist() == [180, 30]
+    assert run1(w, [])["t1"].tolist() == [180, 100]
+    with pytest.raises(oracle.OracleError):
+        oracle.simulate(w, segment_cycles=3)
+
+
 def test_cycles_are_isolated():
     """Each cycle starts from the settled values; an edge later than the
     period still belongs to its cycle and is clipped out of T0/T1."""
