@@ -17,8 +17,10 @@ Also reported (one JSON line):
                 one batch (autotuned, replayed from a captured HIP graph):
                 aggregate gate-cycles/s beside the same jobs run one by one,
                 with every instance's SAIF compared between the two
-  features      gate-eval rate with conditional arcs, with them averaged away
-                and with interconnect delays added (the paper's feature study)
+  features      gate-eval rate with conditional arcs, with them averaged away,
+                with input-edge-qualified rows added, with interconnect
+                delays added (the paper's feature study), and with cycles
+                run as continuous 16-cycle segments
   served        9 resident netlists, Poisson-arriving window and delay-edit
                 requests (200/s for 60 s): req/s, p50/p99 latency, served
                 gate-cycles/s, and a sample re-run alone and compared
@@ -300,27 +302,36 @@ def averaged_arcs(arcs):
         add["cond_val"].append(0)
         add["rise"].append(int(round(float(np.mean(arcs["rise"][idx])))))
         add["fall"].append(int(round(float(np.mean(arcs["fall"][idx])))))
+        for k in add:
+            if len(add[k]) < len(add["gate"]):
+                add[k].append(0)                 # no other qualifier
     return {k: np.concatenate([out[k], np.array(add[k], dtype=arcs[k].dtype)]) for k in arcs}
 
 
 def run_features(args, torch, synth, G):
     """Cost of the timing features on the 1M-gate design (the paper's feature
     study, Table 7): gate-eval time with conditional arcs (the benchmark's
-    arcs), with them averaged away, and with interconnect delays added."""
+    arcs), with them averaged away, with 10% of pins also carrying
+    input-edge-qualified rows, with interconnect delays added, and with the
+    cycles run as continuous 16-cycle segments instead of one by one."""
     cycles = 2000
     w = synth.scale(n_cycles=cycles)
     net = w["netlist"]
-    variants = [("cond_arcs", w["arcs"], None), ("averaged_arcs", averaged_arcs(w["arcs"]), None),
-                ("cond_arcs_and_wires", w["arcs"], synth.make_wires(2, net, 1, 20))]
+    variants = [("cond_arcs", w["arcs"], None, 1), ("averaged_arcs", averaged_arcs(w["arcs"]), None, 1),
+                ("cond_and_edge_arcs", synth.make_arcs(2, net, 5, 80, 0.10, edge_frac=0.10), None, 1),
+                ("cond_arcs_and_wires", w["arcs"], synth.make_wires(2, net, 1, 20), 1),
+                ("cond_arcs_segments16", w["arcs"], None, 16)]
     res = {}
-    for name, arcs, wires in variants:
+    for name, arcs, wires, seg in variants:
         sim = G.GateSim(device=0, stream=torch.cuda.current_stream(), window_cycles=cycles, timing=True)
         d, s = sim.load_work(dict(w, arcs=arcs, wires=wires))
-        sim.simulate(d, s, 0, cycles)
+        if seg > 1:
+            s = sim.segment_stimulus(s, seg)
+        sim.simulate(d, s, 0, cycles // seg)
         sim.read_saif(d, reset=True)
         sim.stats(reset=True)
         for _ in range(2):
-            sim.simulate(d, s, 0, cycles)
+            sim.simulate(d, s, 0, cycles // seg)
             sim.read_saif(d, reset=True)
         st = sim.stats()
         sim.close()
@@ -329,6 +340,8 @@ def run_features(args, torch, synth, G):
     base = res["averaged_arcs"]
     return {"workload": f"scale-1M, {cycles} cycles", "unit": "gate-cycles/s (gate-eval time)", **res,
             "cond_overhead": round(base / res["cond_arcs"] - 1, 4),
+            "cond_and_edge_overhead": round(base / res["cond_and_edge_arcs"] - 1, 4),
+            "segments16_overhead": round(base / res["cond_arcs_segments16"] - 1, 4),
             "cond_and_wire_overhead": round(base / res["cond_arcs_and_wires"] - 1, 4)}
 
 

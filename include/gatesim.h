@@ -160,6 +160,19 @@ gs_status gs_load_stimulus(gs_ctx *ctx, int32_t design, int32_t period_ps, int32
                            const uint8_t *init, const int64_t *toggle_ptr, const int64_t *toggle_ps,
                            int32_t *stim_id);
 
+/* Continuous segments (the re-simulation of Section 1 without isolating
+ * every cycle): creates a view of stimulus `stim` in which each group of
+ * segment_cycles consecutive cycles, from cycle 0, is one cycle.  Every call
+ * that takes the new id then runs each group as one continuous simulation
+ * from the settled state at its start, so edges and pending events cross
+ * the cycle boundaries inside it.  Cycle indices, waveform readback and
+ * T0/T1 count segments; the glitch toggles of gs_read_saif_ig count each
+ * segment's edges beyond its net value change (an upper bound on its
+ * glitches).  The view shares the device arrays of `stim`.  Needs n_cycles
+ * to be a multiple of segment_cycles and segment_cycles x period_ps <= 2^24.
+ * Errors: GS_E_INVALID.  *stim_id receives the new id. */
+gs_status gs_segment_stimulus(gs_ctx *ctx, int32_t stim, int32_t segment_cycles, int32_t *stim_id);
+
 /* Re-simulates cycles [cycle_begin, cycle_end) of stimulus `stim` on
  * `design` and ADDS the per-net SAIF counts into the design's accumulators.
  * The range is processed in windows that fit the memory budget; under the

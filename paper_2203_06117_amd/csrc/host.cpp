@@ -305,7 +305,7 @@ extern "C" gs_status gs_destroy(gs_ctx *ctx)
     }
     for (Stim *s : ctx->stims) {
         if (!s) continue;
-        gs_dev_free(s->d_init); gs_dev_free(s->d_tp); gs_dev_free(s->d_ts);
+        if (s->owns) { gs_dev_free(s->d_init); gs_dev_free(s->d_tp); gs_dev_free(s->d_ts); }
         delete s;
     }
     gs_window_release(ctx, &ctx->win);
@@ -592,6 +592,35 @@ extern "C" gs_status gs_load_stimulus(gs_ctx *ctx, int32_t design, int32_t perio
         for (int64_t k = tp[i]; k < tp[i + 1]; k++) s->tog_prefix[toggle_ps[k] / period_ps + 1]++;
     for (int32_t c = 0; c < n_cycles; c++) s->tog_prefix[c + 1] += s->tog_prefix[c];
     ctx->stims.push_back(s);
+    if (stim_id) *stim_id = (int32_t)ctx->stims.size() - 1;
+    return GS_OK;
+}
+
+extern "C" gs_status gs_segment_stimulus(gs_ctx *ctx, int32_t stim, int32_t segment_cycles, int32_t *stim_id)
+{
+    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
+    if (stim < 0 || stim >= (int32_t)ctx->stims.size() || !ctx->stims[stim])
+        return gs_fail(ctx, GS_E_INVALID, "no stimulus %d", stim);
+    const Stim *s = ctx->stims[stim];
+    const int32_t S = segment_cycles;
+    if (S < 1 || s->n_cycles % S)
+        return gs_fail(ctx, GS_E_INVALID, "n_cycles %d is not a multiple of segment_cycles %d", s->n_cycles, S);
+    if ((int64_t)s->period * S > (1 << 24))
+        return gs_fail(ctx, GS_E_INVALID, "segment of %lld ps exceeds 2^24 ps", (long long)s->period * S);
+    // a segment is a cycle of length S x period: the expansion, the walk
+    // and the T0/T1 sums read nothing else
+    Stim *v = new Stim();
+    v->design = s->design;
+    v->period = s->period * S;
+    v->n_cycles = s->n_cycles / S;
+    v->n_toggles = s->n_toggles;
+    v->owns = false;
+    v->d_init = s->d_init;
+    v->d_tp = s->d_tp;
+    v->d_ts = s->d_ts;
+    v->tog_prefix.resize((size_t)v->n_cycles + 1);
+    for (int32_t k = 0; k <= v->n_cycles; k++) v->tog_prefix[k] = s->tog_prefix[(size_t)k * S];
+    ctx->stims.push_back(v);
     if (stim_id) *stim_id = (int32_t)ctx->stims.size() - 1;
     return GS_OK;
 }

@@ -74,6 +74,7 @@ struct Design {
 struct Stim {
     int32_t design = -1, period = 0, n_cycles = 0;
     int64_t n_toggles = 0;
+    bool owns = true;                        // false: a segment view sharing another stimulus's arrays
     uint8_t *d_init = nullptr;
     int64_t *d_tp = nullptr;
     int64_t *d_ts = nullptr;

@@ -97,6 +97,7 @@ _SIGS = {
     "gs_load_arcs": (I32, [P, I32, C.c_int64, P]),
     "gs_load_wires": (I32, [P, I32, P, P]),
     "gs_load_stimulus": (I32, [P, I32, I32, I32, P, P, P, C.POINTER(I32)]),
+    "gs_segment_stimulus": (I32, [P, I32, I32, C.POINTER(I32)]),
     "gs_simulate": (I32, [P, I32, I32, I32, I32]),
     "gs_read_saif": (I32, [P, I32, P, P, P, I32]),
     "gs_read_saif_ig": (I32, [P, I32, P, P, P, P, I32]),
@@ -255,6 +256,13 @@ class GateSim:
         s = I32()
         self._chk(_lib.gs_load_stimulus(self._h, design, int(period), int(n_cycles), _p(i), _p(tp), _p(ts),
                                         C.byref(s)))
+        return s.value
+
+    def segment_stimulus(self, stim, segment_cycles) -> int:
+        """A view of ``stim`` whose cycles are groups of ``segment_cycles``
+        cycles, each simulated continuously (returns the new stimulus id)."""
+        s = I32()
+        self._chk(_lib.gs_segment_stimulus(self._h, int(stim), int(segment_cycles), C.byref(s)))
         return s.value
 
     def load_work(self, work: dict, cells_loaded: bool = False):

@@ -83,6 +83,26 @@ def test_batch_uneven_instances(G):
             same(sim.read_saif_ig(d), oracle.simulate(w), f"design {d}")
 
 
+def test_batch_segmented_stimuli(G):
+    """Jobs on continuous-segment views of their stimuli (segments of 4 and
+    10 cycles) batched with a plain job: every design matches the oracle's
+    segment run."""
+    works = uneven_jobs(3, seed0=700, gmax=1500)
+    seg = [4, 10, 1]
+    for w, S in zip(works, seg):
+        C = w["stimulus"]["n_cycles"]
+        w["stimulus"] = synth.make_stimulus(700 + S, w["netlist"]["n_inputs"], max(S, C - C % S), 800, 0.2, skew=50)
+    with G.GateSim() as sim:
+        ids = [sim.load_work(w, cells_loaded=i > 0) for i, w in enumerate(works)]
+        jobs = []
+        for (d, s), w, S in zip(ids, works, seg):
+            v = sim.segment_stimulus(s, S) if S > 1 else s
+            jobs.append((d, v, 0, w["stimulus"]["n_cycles"] // S))
+        sim.simulate_batch(jobs)
+        for (d, s), w, S in zip(ids, works, seg):
+            same(sim.read_saif_ig(d), oracle.simulate(w, segment_cycles=S), f"design {d} S {S}")
+
+
 def test_batch_repeated_design_and_ranges(G):
     """One design in several jobs with different cycle ranges: the counts add up."""
     w = synth.small_random(77, 900, 20, 18, 200, 500, 0.3, 3, 50, cond_frac=0.1)
