@@ -345,7 +345,10 @@ static int32_t pin_state(const Design *d, const int32_t *pin_val, int32_t g)
  * ig (may be NULL) gets the glitch toggles (SAIF's IG; the paper's SAIF
  * output, Section 3, read as follows): in a cycle whose list has L edges,
  * at most one edge is functional (the settled value changes iff L is odd),
- * so the cycle adds L - (L mod 2) glitch toggles.
+ * so the cycle adds L - (L mod 2) glitch toggles.  ig_cycle (may be NULL,
+ * length cycle_end - cycle_begin) gets the same toggles summed over all
+ * nets per cycle: the cycle-by-cycle glitch profile whose peaks are the
+ * hot spots the glitch-optimization flow of Section 4 looks for.
  *
  * Probes: for probe p, if cycle_begin <= probe_cycle[p] < cycle_end, the
  * initial value, edge count and up to probe_cap edge times of net
@@ -358,7 +361,7 @@ static int32_t pin_state(const Design *d, const int32_t *pin_val, int32_t g)
 int32_t oracle_run(void *p, int32_t period, int32_t n_cycles,
                    const uint8_t *init, const int64_t *toggle_ptr, const int64_t *toggle_ps,
                    int32_t cycle_begin, int32_t cycle_end,
-                   int64_t *tc, int64_t *t0, int64_t *t1, int64_t *ig,
+                   int64_t *tc, int64_t *t0, int64_t *t1, int64_t *ig, int64_t *ig_cycle,
                    int32_t n_probe, const int32_t *probe_net, const int32_t *probe_cycle,
                    int32_t *probe_init, int32_t *probe_len, int32_t *probe_times, int32_t probe_cap,
                    int64_t *stats)
@@ -509,6 +512,7 @@ int32_t oracle_run(void *p, int32_t period, int32_t n_cycles,
             int64_t a = cnt[n], b = cnt[n + 1];
             tc[n] += b - a;
             if (ig) ig[n] += (b - a) - ((b - a) & 1);
+            if (ig_cycle) ig_cycle[c - cycle_begin] += (b - a) - ((b - a) & 1);
             /* time at 1 and time at 0 in [0, T), summed segment by segment */
             int32_t v = start_val[n];
             int64_t prev = 0, on = 0, off = 0;

@@ -52,9 +52,12 @@ def test_oracle_matches_brute(mode):
             assert (pinit, ptimes) == waves[(n, c)], (seed, n, c)
         # glitch toggles from the brute model's lists: all but the cycle's functional edge
         ig = [0] * N
+        ig_cycle = [0] * C
         for (n, c), (_, times) in waves.items():
             ig[n] += len(times) - len(times) % 2
+            ig_cycle[c] += len(times) - len(times) % 2
         assert r["ig"].tolist() == ig, seed
+        assert r["ig_cycle"].tolist() == ig_cycle, seed
         n_ok += 1
     assert n_ok == 120
 
@@ -119,6 +122,8 @@ def test_oracle_invariants(which):
     sample = [(int(n), int(c)) for n, c in zip(rng.integers(0, N, 300), rng.integers(b, e, 300))]
     r = oracle.simulate(w, b, e, probes=sample)
     assert np.all(r["t0"] + r["t1"] == (e - b) * T)
+    assert r["ig_cycle"].shape == (e - b,) and r["ig_cycle"].sum() == r["ig"].sum()
+    assert np.array_equal(r["ig_cycle"][:5], oracle.simulate(w, b, b + 5)["ig_cycle"])
     s_b = _settle_numpy(net, _inputs_at(stim, b * T))
     s_e = _settle_numpy(net, _inputs_at(stim, e * T))
     assert np.array_equal(r["tc"] % 2, s_b ^ s_e)

@@ -164,6 +164,7 @@ def test_xor_glitch_generator():
             assert times == [10 + lo + rx, 10 + hi + fx], (a, b, rx, fx)
             assert r["ig"][3] == 2 and r["tc"][3] == 2      # the whole pulse is a glitch
         assert r["ig"][:3].tolist() == [0, 0, 0]            # one functional edge on the input and buffers
+        assert r["ig_cycle"].tolist() == [r["ig"][3]]       # the cycle's profile entry holds the pulse
 
 
 def test_msi_min_delay():
