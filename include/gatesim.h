@@ -160,6 +160,19 @@ gs_status gs_load_stimulus(gs_ctx *ctx, int32_t design, int32_t period_ps, int32
                            const uint8_t *init, const int64_t *toggle_ptr, const int64_t *toggle_ps,
                            int32_t *stim_id);
 
+/* Per-cycle glitch profile, whose peaks are the glitch hot spots that the
+ * glitch-optimization flow of Section 4 targets: re-simulates cycles
+ * [cycle_begin, cycle_end) exactly as gs_simulate does (adding the SAIF
+ * counts) and writes into per_cycle[c - cycle_begin] the glitch toggles of
+ * cycle c summed over all nets of the design (each net's edge count in the
+ * cycle less its parity; summed over the range it equals the sum of
+ * gs_read_saif_ig's per-net glitch toggles).  per_cycle: caller-owned host
+ * array of cycle_end - cycle_begin entries.  Costs one extra pass over each
+ * window's per-lane edge counts (2 bytes per net and cycle) and a small
+ * device allocation per call.  Errors: as gs_simulate. */
+gs_status gs_glitch_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end,
+                            int64_t *per_cycle);
+
 /* Continuous segments (the re-simulation of Section 1 without isolating
  * every cycle): creates a view of stimulus `stim` in which each group of
  * segment_cycles consecutive cycles, from cycle 0, is one cycle.  Every call

@@ -159,6 +159,10 @@ hipError_t launch_cone_place(const GateRec *gates, const PinRec *pins, uint32_t 
 hipError_t launch_edit_apply(const EditRec *ed, uint32_t n, const int32_t *slot, PinRec *cp, uint32_t stride,
                              uint32_t n_cone, hipStream_t s);
 // Zeroes the SAIF counters of the output nets of gates[0 .. n).
+// Adds, for every cycle of a finished window, the glitch toggles of nets
+// [0, n_nets) (edge count less its parity) into out[cycle].
+hipError_t launch_glitch_profile(const uint16_t *ends, uint32_t n_nets, uint32_t tiles, uint32_t cycles,
+                                 unsigned long long *out, hipStream_t s);
 hipError_t launch_saif_zero(const GateRec *gates, uint32_t n, SaifAcc acc, hipStream_t s);
 
 }  // namespace gs

@@ -1222,6 +1222,49 @@ hipError_t launch_cone_place(const GateRec *gates, const PinRec *pins, uint32_t 
     return hipGetLastError();
 }
 
+// Per-cycle glitch profile of a finished window.  One wave per (64-cycle
+// tile, group of kProfileNets nets), lane = cycle, tiles fastest so that
+// neighbouring waves read neighbouring lines of a net; a lane's edge count
+// is its inclusive end less its left neighbour's.  One atomic add per lane.
+// The difference is written as an addition of the shifted negation: a
+// subtraction would be fused with the lane shift into a reversed-operand
+// form, which gave the negated count on this chip.
+constexpr uint32_t kProfileNets = 2048;
+
+__global__ __launch_bounds__(256) void glitch_profile_kernel(const uint16_t *__restrict__ ends, uint32_t n_nets,
+                                                             uint32_t tiles, uint32_t cycles,
+                                                             unsigned long long *__restrict__ out, uint64_t n_waves)
+{
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + threadIdx.x / kLanes;
+    if (w >= n_waves) return;                                   // whole waves leave together
+    const uint32_t lane = threadIdx.x % kLanes;
+    const uint32_t tile = (uint32_t)(w % tiles);
+    const uint32_t n0 = (uint32_t)(w / tiles) * kProfileNets;
+    const uint32_t n1 = min(n_nets, n0 + kProfileNets);
+    const uint64_t stride = (uint64_t)tiles * kLanes;
+    const uint16_t *p = ends + ((uint64_t)n0 * tiles + tile) * kLanes;
+    uint32_t acc = 0;                                           // at most kProfileNets x kMaxChunk
+#pragma unroll 8
+    for (uint32_t n = n0; n < n1; n++, p += stride) {
+        const uint32_t e = ld_u16(p, lane) & kEndCount;
+        const uint32_t c = e + wave_shr1(0u - e);
+        acc += c - (c & 1u);
+    }
+    const uint32_t cyc = tile * kLanes + lane;
+    if (cyc < cycles && acc)
+        __hip_atomic_fetch_add(glob(out + cyc), (unsigned long long)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+hipError_t launch_glitch_profile(const uint16_t *ends, uint32_t n_nets, uint32_t tiles, uint32_t cycles,
+                                 unsigned long long *out, hipStream_t s)
+{
+    if (n_nets == 0 || tiles == 0) return hipSuccess;
+    const uint64_t n_waves = (uint64_t)((n_nets + kProfileNets - 1) / kProfileNets) * tiles;
+    hipLaunchKernelGGL(glitch_profile_kernel, dim3((unsigned)((n_waves + 3) / 4)), dim3(256), 0, s, ends, n_nets, tiles,
+                       cycles, out, n_waves);
+    return hipGetLastError();
+}
+
 // Writes edited arc delays into the cone's pin records.
 __global__ void edit_apply_kernel(const EditRec *__restrict__ ed, uint32_t n, const int32_t *__restrict__ slot,
                                   PinRec *cp, uint32_t stride, uint32_t n_cone)

@@ -264,6 +264,10 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
         ctx->stats.window_retries++;
         return GS_OK;
     }
+    if (ctx->d_profile)
+        for (const Piece &p : pieces)
+            HIPCHK(launch_glitch_profile(ctx->win.ends + p.chunk_base * kLanes, (uint32_t)p.d->N, (uint32_t)p.tiles,
+                                         (uint32_t)p.cycles, ctx->d_profile + (p.c0 - ctx->profile_begin), hs));
     ctx->stats.gate_eval_ms += res.gate_eval_ms;
     ctx->stats.expand_ms += res.expand_ms;
     ctx->stats.gate_eval_launches += res.launches;
@@ -396,6 +400,41 @@ void gs_graph_cache_clear(gs_ctx *ctx)
         gs_dev_free(kv.second.segs);
     }
     ctx->graphs.clear();
+}
+
+extern "C" gs_status gs_glitch_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin,
+                                      int32_t cycle_end, int64_t *per_cycle)
+{
+    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
+    if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
+    gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
+    if (st) return st;
+    const int32_t n = cycle_end - cycle_begin;
+    if (n > 0 && !per_cycle) return gs_fail(ctx, GS_E_INVALID, "null per_cycle");
+    (void)hipSetDevice(ctx->opt.device);
+    unsigned long long *prof = nullptr;
+    if (hipMalloc((void **)&prof, sizeof(unsigned long long) * std::max(n, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return gs_fail(ctx, GS_E_NOMEM, "cannot allocate the glitch profile");
+    }
+    hipError_t he = launch_fill_u64(prof, (uint64_t)std::max(n, 1), 0ull, ctx->stream);
+    if (he != hipSuccess) {
+        gs_dev_free(prof);
+        return gs_fail(ctx, GS_E_DEVICE, "%s", hipGetErrorString(he));
+    }
+    ctx->d_profile = prof;
+    ctx->profile_begin = cycle_begin;
+    st = gs_simulate(ctx, design, stim, cycle_begin, cycle_end);
+    ctx->d_profile = nullptr;
+    std::vector<unsigned long long> h((size_t)std::max(n, 1));
+    if (!st && (hipMemcpyAsync(h.data(), prof, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                               ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess))
+        st = gs_fail(ctx, GS_E_DEVICE, "glitch profile readback failed");
+    gs_dev_free(prof);
+    if (st) return st;
+    for (int32_t c = 0; c < n; c++) per_cycle[c] = (int64_t)h[c];
+    return GS_OK;
 }
 
 extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end)

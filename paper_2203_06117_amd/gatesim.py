@@ -98,6 +98,7 @@ _SIGS = {
     "gs_load_wires": (I32, [P, I32, P, P]),
     "gs_load_stimulus": (I32, [P, I32, I32, I32, P, P, P, C.POINTER(I32)]),
     "gs_segment_stimulus": (I32, [P, I32, I32, C.POINTER(I32)]),
+    "gs_glitch_profile": (I32, [P, I32, I32, I32, I32, P]),
     "gs_simulate": (I32, [P, I32, I32, I32, I32]),
     "gs_read_saif": (I32, [P, I32, P, P, P, I32]),
     "gs_read_saif_ig": (I32, [P, I32, P, P, P, P, I32]),
@@ -257,6 +258,13 @@ class GateSim:
         self._chk(_lib.gs_load_stimulus(self._h, design, int(period), int(n_cycles), _p(i), _p(tp), _p(ts),
                                         C.byref(s)))
         return s.value
+
+    def glitch_profile(self, design, stim, cycle_begin, cycle_end) -> np.ndarray:
+        """Simulates like ``simulate`` and returns the glitch toggles of every
+        cycle of the range summed over all nets (int64 array)."""
+        out = np.zeros(max(0, int(cycle_end) - int(cycle_begin)), dtype=np.int64)
+        self._chk(_lib.gs_glitch_profile(self._h, int(design), int(stim), int(cycle_begin), int(cycle_end), _p(out)))
+        return out
 
     def segment_stimulus(self, stim, segment_cycles) -> int:
         """A view of ``stim`` whose cycles are groups of ``segment_cycles``

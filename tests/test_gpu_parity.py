@@ -143,6 +143,35 @@ def test_continuous_segments(G, S):
         assert not np.array_equal(iso["t1"], ref["t1"])
 
 
+@pytest.mark.parametrize("opt", [dict(), dict(window_cycles=37), dict(window_cycles=100, hbm_budget=1_900_000),
+                                 dict(schedule=1)])
+def test_glitch_profile(G, opt):
+    """Per-cycle glitch toggles over all nets against the oracle's profile,
+    for a sub-range run whole, in windows, split by a tight budget and from
+    captured graphs; the profile sums to the per-net glitch counts.  With
+    default options also on a continuous-segment view (one entry per
+    segment)."""
+    w = synth.small_random(95, 1500, 40, 25, 300, 500, 0.4, 2, 70, cond_frac=0.2, extra=2, extra_p=0.3,
+                           edge_frac=0.2)
+    b, e = 13, 290
+    ref = oracle.simulate(w, b, e)
+    say("profile", opt)
+    with G.GateSim(**opt) as sim:
+        d, s = sim.load_work(w)
+        prof = sim.glitch_profile(d, s, b, e)
+        tc, t0, t1, ig = sim.read_saif_ig(d, reset=True)
+        assert len(prof) == e - b and prof.any()
+        assert np.array_equal(prof, ref["ig_cycle"])
+        assert prof.sum() == ig.sum()
+        assert_same(w, (tc, t0, t1, [], {}, ig), ref, f"profile {opt}")
+        assert len(sim.glitch_profile(d, s, 5, 5)) == 0
+        if not opt:
+            v = sim.segment_stimulus(s, 5)
+            sim.read_saif_ig(d, reset=True)
+            prof = sim.glitch_profile(d, v, 2, 60)
+            assert np.array_equal(prof, oracle.simulate(w, 2, 60, segment_cycles=5)["ig_cycle"])
+
+
 def test_tiny_config_waveforms(G):
     """2,000 gates x 100 cycles: all SAIF counts plus a sample of full
     waveforms (the analog of the paper's spot-checks)."""
@@ -286,7 +315,8 @@ def test_scale_config_sample(G):
     runs cycles [0, 990) and [0, 1010); under cycle isolation their SAIF
     difference is cycles 990..1009, which straddle the first window boundary
     and are compared net by net with the oracle, plus a waveform sample from
-    the resident second window."""
+    the resident second window and the per-cycle glitch profile of those
+    cycles."""
     w = synth.scale(n_cycles=1100)
     b, e = 990, 1010
     N = 20_000 + 1_000_000
@@ -299,11 +329,12 @@ def test_scale_config_sample(G):
         d, s = sim.load_work(w)
         sim.simulate(d, s, 0, b)
         lo = sim.read_saif(d, reset=True)
-        sim.simulate(d, s, 0, e)
+        prof = sim.glitch_profile(d, s, 0, e)
         hi = sim.read_saif(d, reset=True)
         waves = [sim.read_waveform(d, s, n, c) for n, c in probes]
     got = tuple(h - l for h, l in zip(hi, lo))
     assert_same(w, got, ref, "scale")
+    assert np.array_equal(prof[b:e], ref["ig_cycle"])
     for (n, c), g_, o_ in zip(probes, waves, ref["probes"]):
         assert g_ == o_, (n, c)
 
