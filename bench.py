@@ -337,8 +337,29 @@ def run_features(args, torch, synth, G):
         sim.close()
         res[name] = round(2 * net["n_gates"] * cycles / (st["gate_eval_ms"] / 1e3), 1)
         log(f"features: {name} {res[name]:.3g} gate-cycles/s (gate-eval time only)")
+    # the per-cycle glitch profile: the same simulation plus one pass over
+    # the window's lane counts, end to end against the plain simulation
+    sim = G.GateSim(device=0, stream=torch.cuda.current_stream(), window_cycles=cycles)
+    d, s = sim.load_work(w)
+    sim.simulate(d, s, 0, cycles)
+    sim.glitch_profile(d, s, 0, cycles)
+    wall = {}
+    for name in ("simulate", "glitch_profile"):
+        fn = getattr(sim, name)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            fn(d, s, 0, cycles)
+        torch.cuda.synchronize()
+        wall[name] = (time.perf_counter() - t) / 3 * 1e3
+    prof = sim.glitch_profile(d, s, 0, cycles)
+    sim.close()
+    log(f"features: simulate {wall['simulate']:.2f} ms, with glitch profile {wall['glitch_profile']:.2f} ms "
+        f"(peak cycle {int(prof.argmax())}: {int(prof.max())} glitch toggles, mean {prof.mean():.0f})")
     base = res["averaged_arcs"]
     return {"workload": f"scale-1M, {cycles} cycles", "unit": "gate-cycles/s (gate-eval time)", **res,
+            "simulate_ms": round(wall["simulate"], 3), "glitch_profile_ms": round(wall["glitch_profile"], 3),
+            "glitch_profile_overhead": round(wall["glitch_profile"] / wall["simulate"] - 1, 4),
             "cond_overhead": round(base / res["cond_arcs"] - 1, 4),
             "cond_and_edge_overhead": round(base / res["cond_and_edge_arcs"] - 1, 4),
             "segments16_overhead": round(base / res["cond_arcs_segments16"] - 1, 4),

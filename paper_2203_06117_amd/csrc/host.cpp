@@ -204,7 +204,7 @@ extern "C" gs_status gs_check_stimulus(int32_t n_inputs, int32_t period_ps, int3
 extern "C" void gs_default_options(gs_options *o)
 {
     std::memset(o, 0, sizeof(*o));
-    o->lds_cap = 8;
+    o->lds_cap = 0;
     o->waves_per_block = 4;
     o->tiles_per_wave = 8;
     o->schedule = GS_SCHED_LEVELS;
@@ -235,6 +235,7 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
     gs_options o;
     if (opt) o = *opt;
     else gs_default_options(&o);
+    const bool auto_cap = o.lds_cap == 0;
     if (o.lds_cap == 0) o.lds_cap = 8;
     if (o.waves_per_block == 0) o.waves_per_block = 4;
     if (o.tiles_per_wave == 0) o.tiles_per_wave = 8;
@@ -254,6 +255,7 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
     if (hipSetDevice(o.device) != hipSuccess) return gs_fail(nullptr, GS_E_DEVICE, "hipSetDevice failed");
     gs_ctx *ctx = new gs_ctx();
     ctx->opt = o;
+    ctx->auto_cap = auto_cap;
     if (o.stream) {
         ctx->stream = (hipStream_t)o.stream;
         ctx->own_stream = false;

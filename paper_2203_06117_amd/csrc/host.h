@@ -104,6 +104,7 @@ struct GraphEntry {
 
 struct gs_ctx {
     gs_options opt;
+    bool auto_cap = false;                   // lds_cap left to the library: sized per round by tuning_for
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;

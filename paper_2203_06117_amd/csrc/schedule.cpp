@@ -43,6 +43,24 @@ Tuning current_tuning(const gs_ctx *ctx)
     return Tuning{ctx->opt.lds_cap, ctx->opt.waves_per_block, ctx->opt.tiles_per_wave};
 }
 
+// The tuning for a round of pieces: the context's, except that an LDS
+// output cap left to the library is sized by the densest piece's input
+// toggles per (input, cycle).  A lane of a segment view carries the events
+// of many cycles; with the single-cycle cap most of its lanes would take
+// the spill path.
+Tuning tuning_for(const gs_ctx *ctx, const std::vector<Piece> &ps)
+{
+    Tuning t = current_tuning(ctx);
+    if (!ctx->auto_cap) return t;
+    double rho = 0;
+    for (const Piece &p : ps) {
+        const int64_t tog = p.s->tog_prefix[p.c0 + p.cycles] - p.s->tog_prefix[p.c0];
+        rho = std::max(rho, (double)tog / ((double)std::max(1, p.d->I) * std::max(1, p.cycles)));
+    }
+    t.cap = rho <= 0.5 ? 8 : rho <= 1.0 ? 16 : 32;
+    return t;
+}
+
 uint64_t chunks_of(const Piece &p)
 {
     return (uint64_t)p.d->N * (uint64_t)p.tiles;
@@ -453,7 +471,7 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
         pieces.push_back(make_piece(ctx, design, stim, c0, std::min(W, cycle_end - c0)));
     // one window per round: windows run one after another
     for (const Piece &p : pieces) {
-        st = run_pieces(ctx, std::vector<Piece>{p}, current_tuning(ctx), true, ctx->opt.timing != 0, nullptr);
+        st = run_pieces(ctx, std::vector<Piece>{p}, tuning_for(ctx, {p}), true, ctx->opt.timing != 0, nullptr);
         if (st) return st;
     }
     ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
@@ -487,6 +505,7 @@ static gs_status autotune_impl(gs_ctx *ctx, const std::vector<Piece> &trial, Tun
     ctx->opt.lds_cap = bt.cap;
     ctx->opt.waves_per_block = bt.wpb;
     ctx->opt.tiles_per_wave = bt.tpw;
+    ctx->auto_cap = false;                            // the tuned cap stays
     if (best_out) *best_out = bt;
     if (best_ms) *best_ms = best;
     return GS_OK;
@@ -566,7 +585,7 @@ extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job
             ctx->opt.tiles_per_wave = it->second[2];
         }
     }
-    gs_status st = run_pieces(ctx, pieces, current_tuning(ctx), true, ctx->opt.timing != 0, nullptr);
+    gs_status st = run_pieces(ctx, pieces, tuning_for(ctx, pieces), true, ctx->opt.timing != 0, nullptr);
     if (st) return st;
     ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
     return GS_OK;

@@ -209,12 +209,13 @@ def test_dense_activity(G):
     output lists outgrow the LDS staging; both paths must match the oracle."""
     w = synth.small_random(77, 600, 16, 12, 200, 2000, 0.9, 2, 60, cond_frac=0.2, extra=6, extra_p=0.9,
                            edge_frac=0.3)
-    for opt in (dict(), dict(tiles_per_wave=2, lds_cap=4)):
+    for opt in (dict(lds_cap=8), dict(tiles_per_wave=2, lds_cap=4), dict()):
         say("dense", opt)
         got = gpu_saif(G, w, **opt)
         assert_same(w, got, oracle.simulate(w), f"dense {opt}")
         assert got[4]["unstaged_groups"] > 0
-        assert got[4]["spilled_lanes"] > 0
+        if opt:                                   # the automatic cap (32 here) may leave no lane over it
+            assert got[4]["spilled_lanes"] > 0
 
 
 @pytest.mark.parametrize("opt", [dict(), dict(tiles_per_wave=3), dict(lds_cap=4, waves_per_block=2)])
