@@ -45,8 +45,9 @@ def algorithmic_bytes(net, tc, n_cycles, n_tiles):
     """Bytes the gate-evaluation kernel must move for the simulated cycles:
     per gate, every fanin list is read once per sink and the output list is
     written once (4 B per transition, 2 B lane end + 16 B chunk header per
-    64-cycle tile per list), plus the gate's 32 B record, 32 B per pin and
-    24 B of SAIF atomics per tile."""
+    64-cycle tile per list), plus the gate's 32 B record, 48 B per pin
+    (net, condition pin, 8-entry delay row, wire delays) and 24 B of SAIF
+    atomics per tile."""
     I, Gn = net["n_inputs"], net["n_gates"]
     fp, fn = net["fanin_ptr"], net["fanin_net"]
     k = np.diff(fp)
@@ -54,7 +55,7 @@ def algorithmic_bytes(net, tc, n_cycles, n_tiles):
     list_writes = 4.0 * tc[I:].sum()
     hdr_per_list = 2.0 * n_cycles + 16.0 * n_tiles
     headers = hdr_per_list * (k.sum() + Gn)
-    meta = (32.0 + 32.0 * k.sum() / max(Gn, 1) + 24.0) * Gn * n_tiles
+    meta = (32.0 + 48.0 * k.sum() / max(Gn, 1) + 24.0) * Gn * n_tiles
     return list_reads + list_writes + headers + meta
 
 
@@ -149,7 +150,9 @@ def run_scale(args, torch, synth, GateSim):
     log(f"{args.steps} steps in {elapsed:.3f}s")
     tc = saif[0]
     # glitch share of the output toggles, read once after the timed steps
-    sim.simulate(d, s, 0, min(C, 1000))
+    # (over the same window, so that every gate-eval launch of this leg has
+    # the timed launches' shape and a kernel trace averages like the events)
+    sim.simulate(d, s, 0, C)
     g_tc, _, _, g_ig = sim.read_saif_ig(d, reset=True)
     glitch_share = float(g_ig[net["n_inputs"]:].sum()) / max(1.0, float(g_tc[net["n_inputs"]:].sum()))
     n_tiles_total = sum((min(window, C - c0) + 63) // 64 for c0 in range(0, C, window))
