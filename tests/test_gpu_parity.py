@@ -299,6 +299,61 @@ def test_errors(G):
         sim.simulate(d, s, 0, 0)                              # empty range is fine
 
 
+def test_capacity_errors(G):
+    """More than 32,767 transitions in one (net, 64-cycle tile) is reported
+    as GS_E_CAPACITY, from the expansion (one input with 520 toggles per
+    cycle) and from a gate (an XOR2 of two inputs toggling on alternate
+    picoseconds, 624 output edges per cycle); the chunk is written empty,
+    nothing is committed, and the context keeps working."""
+    T, C = 1000, 64
+    heavy = [[c * T + t for c in range(C) for t in range(520)]]
+    w = work(1, [("BUF", [0])], (1, 1), heavy, [0], period=T, n_cycles=C)
+    even = [c * T + t for c in range(C) for t in range(0, 624, 2)]
+    odd = [c * T + t for c in range(C) for t in range(1, 624, 2)]
+    w2 = work(2, [("XOR2", [0, 1])], (1, 1), [even, odd], [0, 0], period=T, n_cycles=C)
+    ok = synth.small_random(5, 300, 16, 12, 150, 400, 0.3, 3, 40, cond_frac=0.2)
+    with G.GateSim() as sim:
+        sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)
+        for case, ww in (("input", w), ("gate", w2)):
+            say("capacity", case)
+            d, s = sim.load_work(ww, cells_loaded=True)
+            with pytest.raises(G.GateSimError) as e:
+                sim.simulate(d, s, 0, C)
+            assert e.value.status == G.GS_E_CAPACITY, case
+            tc, t0, t1 = sim.read_saif(d)
+            assert not tc.any() and not t1.any(), case
+        d, s = sim.load_work(ok, cells_loaded=True)
+        sim.simulate(d, s, 0, 150)
+        tc, t0, t1, ig = sim.read_saif_ig(d)
+    assert_same(ok, (tc, t0, t1, [], {}, ig), oracle.simulate(ok), "after capacity errors")
+
+
+def test_entry_point_errors(G):
+    """Segment views and the glitch profile reject what they cannot do."""
+    w = synth.small_random(3, 100, 8, 5, 10, 200, 0.3, 2, 9)
+    with G.GateSim() as sim:
+        d, s = sim.load_work(w)
+        for seg in (0, 3, 11):                                # 10 cycles: not a positive divisor
+            with pytest.raises(G.GateSimError) as e:
+                sim.segment_stimulus(s, seg)
+            assert e.value.status == G.GS_E_INVALID, seg
+        st = w["stimulus"]
+        s3 = sim.load_stimulus(d, 1 << 23, 4, st["init"], np.zeros(9, dtype=np.int64), np.zeros(0, dtype=np.int64))
+        with pytest.raises(G.GateSimError) as e:
+            sim.segment_stimulus(s3, 4)                       # 2^25 ps segments
+        assert e.value.status == G.GS_E_INVALID
+        v = sim.segment_stimulus(s3, 2)                       # 2^24 ps is allowed
+        with pytest.raises(G.GateSimError) as e:
+            sim.simulate(d, v, 0, 3)                          # the view has 2 cycles
+        assert e.value.status == G.GS_E_INVALID
+        with pytest.raises(G.GateSimError) as e:
+            sim.glitch_profile(d, s, 4, 12)
+        assert e.value.status == G.GS_E_INVALID
+        with pytest.raises(G.GateSimError) as e:
+            sim.glitch_profile(d, 99, 0, 2)
+        assert e.value.status == G.GS_E_INVALID
+
+
 def test_edge_cases(G):
     # inputs that never toggle, a gate-free design, single-cycle stimulus
     w = synth.small_random(21, 400, 12, 10, 1, 300, 0.0, 2, 40)
