@@ -2,10 +2,12 @@
 
 All results are integers (picosecond times, counts, SAIF sums), so the bar
 is equality.  Cases cover hand-derived circuits, seeded random netlists with
-wires, conditional arcs, multi-edge inputs and zero-delay mode, window and
-tile invariance (ragged last tiles, window boundaries, forced arena
-retries, forced on-chip staging overflow), the levelizer, error paths, and
-the 1M-gate workload in the launch configuration the benchmark times.
+wires, conditional and input-edge-qualified arcs, multi-edge inputs and
+zero-delay mode, continuous segments, the per-cycle glitch profile, window
+and tile invariance (ragged last tiles, window boundaries, forced arena
+retries, forced on-chip staging overflow), the levelizer, error paths
+(capacity overflow from inputs and from gates included), and the 1M-gate
+workload in the launch configuration the benchmark times.
 """
 import json
 import os
