@@ -86,7 +86,8 @@ typedef struct {
     int32_t  timing;          /* nonzero: time every gate-evaluation launch with HIP events (gs_get_stats) */
     int32_t  tiles_per_wave;  /* consecutive 64-cycle tiles of one gate evaluated by one wave; 0 = 8 */
     int32_t  autotune;        /* nonzero: gs_simulate_batch picks lds_cap, waves_per_block and tiles_per_wave by
-                                 timing candidates on its largest job (once per batch shape) */
+                                 timing candidates on the batch, each job cut to 2,048 cycles (once per batch
+                                 shape; another setting must beat the default by 3%) */
     int32_t  reserved[5];
 } gs_options;
 

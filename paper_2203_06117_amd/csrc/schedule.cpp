@@ -479,10 +479,13 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
 }
 
 // Times each candidate tuning on a trial window (nothing committed) and
-// keeps the fastest in the context.
+// keeps the fastest in the context.  The staging caps tried are the one
+// the trial's toggle density calls for (or the caller's), half and twice it.
 static gs_status autotune_impl(gs_ctx *ctx, const std::vector<Piece> &trial, Tuning *best_out, double *best_ms)
 {
-    static const Tuning cands[] = {{8, 4, 8}, {8, 4, 4}, {8, 2, 8}, {8, 4, 16}, {16, 4, 8}, {8, 8, 8}, {8, 4, 2}, {4, 4, 8}};
+    const int32_t c = tuning_for(ctx, trial).cap;
+    const int32_t lo = std::max(4, c / 2), hi = std::min(32, c * 2);
+    const Tuning cands[] = {{c, 4, 8}, {c, 4, 4}, {c, 2, 8}, {c, 4, 16}, {hi, 4, 8}, {c, 8, 8}, {c, 4, 2}, {lo, 4, 8}};
     double best = 1e30;
     Tuning bt = current_tuning(ctx);
     const int saved_sched = ctx->opt.schedule;
@@ -495,7 +498,10 @@ static gs_status autotune_impl(gs_ctx *ctx, const std::vector<Piece> &trial, Tun
         ms = 0;
         st = run_pieces(ctx, trial, t, false, true, &ms);
         if (st) { ctx->opt.schedule = saved_sched; ctx->stats = saved; return st; }
-        if (ms < best) {
+        // the first candidate is the default shape; another replaces the
+        // best so far only when it is clearly faster on the trial, which
+        // stands in for the whole batch only approximately
+        if (ms < (&t == cands ? best : 0.97 * best)) {
             best = ms;
             bt = t;
         }
@@ -548,35 +554,32 @@ extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job
     const uint64_t t_start = gs_now_ns();
     ctx->last = LastWindow();
     std::vector<Piece> pieces;
-    int64_t best_work = -1;
-    Piece trial;
     for (int32_t i = 0; i < n_jobs; i++) {
         const gs_job &j = jobs[i];
         Design *d = ctx->designs[j.design];
         const int32_t W = default_window(ctx, d);
-        for (int32_t c0 = j.cycle_begin; c0 < j.cycle_end; c0 += W) {
+        for (int32_t c0 = j.cycle_begin; c0 < j.cycle_end; c0 += W)
             pieces.push_back(make_piece(ctx, j.design, j.stim, c0, std::min(W, j.cycle_end - c0)));
-            const int64_t work = (int64_t)d->G * pieces.back().cycles;
-            if (work > best_work) {
-                best_work = work;
-                trial = pieces.back();
-            }
-        }
     }
     if (pieces.empty()) return GS_OK;
     if (ctx->opt.autotune) {
-        // tune once per batch shape on (up to 256 cycles of) its largest piece
+        // tune once per batch shape on the batch itself, each piece cut to
+        // at most 2,048 cycles: a trial of one piece, or of a few hundred
+        // cycles, favours settings that lose on the whole uneven mix
         std::string key;
         for (const Piece &p : pieces) {
             key += std::to_string(p.di) + ":" + std::to_string(p.cycles) + ",";
         }
         auto it = ctx->tuned.find(key);
         if (it == ctx->tuned.end()) {
-            trial.cycles = std::min(trial.cycles, 256);
-            trial.tiles = (trial.cycles + kLanes - 1) / kLanes;
+            std::vector<Piece> trial = pieces;
+            for (Piece &p : trial) {
+                p.cycles = std::min(p.cycles, 2048);
+                p.tiles = (p.cycles + kLanes - 1) / kLanes;
+            }
             Tuning t;
             double ms;
-            gs_status st = autotune_impl(ctx, std::vector<Piece>{trial}, &t, &ms);
+            gs_status st = autotune_impl(ctx, trial, &t, &ms);
             if (st) return st;
             ctx->tuned[key] = {t.cap, t.wpb, t.tpw};
         } else {
