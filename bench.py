@@ -59,10 +59,11 @@ def algorithmic_bytes(net, tc, n_cycles, n_tiles):
     return list_reads + list_writes + headers + meta
 
 
-def measured_traffic():
-    """HBM bytes per gate-eval launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration), or
-    None when the kernel source has changed since the counters were taken."""
+def measured_counters():
+    """The committed counter summary of the gate-eval kernel on this
+    workload (HBM bytes per launch from FETCH_SIZE and WRITE_SIZE scaled by
+    a copy-kernel calibration; VALU instructions per launch), or None when
+    the kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "gate_eval_scale1M_counters.json")
     if not os.path.exists(path):
@@ -73,7 +74,7 @@ def measured_traffic():
         h.update(open(os.path.join(ROOT, "paper_2203_06117_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
 
 
 def host_cpu():
@@ -163,14 +164,20 @@ def run_scale(args, torch, synth, GateSim):
         avg_launch_s = st["gate_eval_ms"] / 1e3 / launches
         per_launch_bytes = alg_bytes_step * args.steps / launches
         achieved = per_launch_bytes / avg_launch_s / 1e9
-        traffic = measured_traffic()
+        rec = measured_counters()
+        traffic = rec["traffic_bytes_per_launch"] if rec else None
+        # VALU issue: a wave64 instruction occupies a 16-lane SIMD for 4
+        # cycles; 1,024 SIMDs at the nominal 2.4 GHz
+        valu = rec.get("valu_insts_per_launch") if rec else None
+        valu_frac = round(valu * 4 / 1024 / (avg_launch_s * 2.4e9), 4) if valu else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "traffic_gbs": round(traffic / avg_launch_s / 1e9, 1) if traffic else None,
                     "copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
                     "kernel": "gate_eval_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
                     "launches": launches, "bytes_per_launch": round(per_launch_bytes),
-                    "bytes_per_gate_cycle": round(alg_bytes_step / (Gn * C), 3)}
+                    "bytes_per_gate_cycle": round(alg_bytes_step / (Gn * C), 3),
+                    "valu_insts_per_launch": valu, "valu_issue_frac": valu_frac}
     cpu = None
     if args.cpu_cycles > 0:
         import oracle
