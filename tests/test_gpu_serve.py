@@ -162,3 +162,33 @@ def test_bad_edit_is_rejected(served):
     r = sim.poll(t, wait=True)
     sim.release(t)
     assert r["status"] != 0
+
+
+def test_segment_view_served(G):
+    """A continuous-segment view of a stimulus is served like any other:
+    window and delay-edit requests on 5-cycle segments match the oracle's
+    segment runs (the serving loop keeps the single-cycle staging cap, so
+    long lanes take the spill path)."""
+    S = 5
+    w = synth.small_random(640, 900, 20, 15, 200, 300, 0.3, 3, 70, cond_frac=0.1, edge_frac=0.2)
+    sim = G.GateSim()
+    started = False
+    try:
+        d, s = sim.load_work(w)
+        v = sim.segment_stimulus(s, S)
+        sim.serve_start([(d, v, 0, 40)], max_queue=64)
+        started = True
+        say("segment view served")
+        tw = sim.submit_window(d, v, 3, 29)
+        edits = random_edits(np.random.default_rng(3), w, 12)
+        te = sim.submit_edit(d, v, edits)
+        r = result_of(sim, tw)
+        ref = oracle.simulate(w, 3, 29, segment_cycles=S)
+        same((r["tc"], r["t0"], r["t1"], r["ig"]), (ref["tc"], ref["t0"], ref["t1"], ref["ig"]), "segment window")
+        r = result_of(sim, te)
+        ref = oracle.simulate(dict(w, arcs=edited_arcs(w["arcs"], edits)), 0, 40, segment_cycles=S)
+        same((r["tc"], r["t0"], r["t1"], r["ig"]), (ref["tc"], ref["t0"], ref["t1"], ref["ig"]), "segment edit")
+    finally:
+        if started:
+            sim.serve_stop()
+        sim.close()
