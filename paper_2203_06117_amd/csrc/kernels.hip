@@ -1238,14 +1238,26 @@ __global__ __launch_bounds__(256) void glitch_profile_kernel(const uint16_t *__r
     const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + threadIdx.x / kLanes;
     if (w >= n_waves) return;                                   // whole waves leave together
     const uint32_t lane = threadIdx.x % kLanes;
-    const uint32_t tile = (uint32_t)(w % tiles);
-    const uint32_t n0 = (uint32_t)(w / tiles) * kProfileNets;
+    // wave-uniform bounds keep the loop scalar, so the unrolled loads below
+    // are all in flight before the first wait
+    const uint32_t tile = uniform((uint32_t)(w % tiles));
+    const uint32_t n0 = uniform((uint32_t)(w / tiles) * kProfileNets);
     const uint32_t n1 = min(n_nets, n0 + kProfileNets);
     const uint64_t stride = (uint64_t)tiles * kLanes;
     const uint16_t *p = ends + ((uint64_t)n0 * tiles + tile) * kLanes;
     uint32_t acc = 0;                                           // at most kProfileNets x kMaxChunk
-#pragma unroll 8
-    for (uint32_t n = n0; n < n1; n++, p += stride) {
+    uint32_t n = n0;
+    for (; n + 8 <= n1; n += 8, p += 8 * stride) {
+        uint32_t e[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) e[u] = ld_u16(p + u * stride, lane) & kEndCount;
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const uint32_t c = e[u] + wave_shr1(0u - e[u]);
+            acc += c - (c & 1u);
+        }
+    }
+    for (; n < n1; n++, p += stride) {
         const uint32_t e = ld_u16(p, lane) & kEndCount;
         const uint32_t c = e + wave_shr1(0u - e);
         acc += c - (c & 1u);
