@@ -74,10 +74,11 @@ def test_handmade_golden(G):
                  fx["toggles"], fx["init"], period=fx["period"], n_cycles=fx["n_cycles"], wires=wires)
         say("golden", f)
         probes = [(x["net"], x["cycle"]) for x in fx["expect"]]
-        got = gpu_saif(G, w, probes=probes)
+        S = fx.get("segment_cycles", 1)
+        got = gpu_saif(G, w, probes=probes, segment=S)
         for x, (init, times, n) in zip(fx["expect"], got[3]):
             assert (init, times) == (x["init"], x["times"]), (f, x)
-        assert_same(w, got, oracle.simulate(w), f)
+        assert_same(w, got, oracle.simulate(w, segment_cycles=S), f)
 
 
 @pytest.mark.parametrize("cell", ["BUF", "INV"])
