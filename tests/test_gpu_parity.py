@@ -7,7 +7,7 @@ zero-delay mode, continuous segments, the per-cycle glitch profile, window
 and tile invariance (ragged last tiles, window boundaries, forced arena
 retries, forced on-chip staging overflow), the levelizer, error paths
 (capacity overflow from inputs and from gates included), and the 1M-gate
-workload in the launch configuration the benchmark times.
+workload in the launch configuration the benchmark times and in windows.
 """
 import json
 import os
@@ -368,14 +368,41 @@ def test_edge_cases(G):
     assert_same(w, gpu_saif(G, w), oracle.simulate(w), "boundary toggles")
 
 
+def test_scale_bench_launch(G):
+    """The 1M-gate workload exactly as the benchmark launches it: all 10,000
+    cycles in one window, default tiles, staging and options.  Ten cycles
+    spread over the run are re-simulated by the oracle; the GPU's waveforms
+    of 60 nets in each and its per-cycle glitch totals must equal the
+    oracle's, and T0 + T1 = C x T for every net."""
+    w = synth.scale()
+    C, T = w["stimulus"]["n_cycles"], w["stimulus"]["period"]
+    N = 20_000 + 1_000_000
+    rng = np.random.default_rng(4)
+    cycles = sorted(int(c) for c in rng.choice(C, 10, replace=False))
+    nets = [int(n) for n in rng.integers(0, N, 60)]
+    say("scale launch: gpu")
+    with G.GateSim() as sim:
+        d, s = sim.load_work(w)
+        prof = sim.glitch_profile(d, s, 0, C)
+        tc, t0, t1 = sim.read_saif(d)
+        waves = {(n, c): sim.read_waveform(d, s, n, c) for c in cycles for n in nets}
+    assert np.all(t0 + t1 == C * T)
+    o = oracle.Oracle(w["netlist"], w["arcs"])
+    for c in cycles:
+        say("scale launch: oracle cycle", c)
+        ref = o.run(w["stimulus"], c, c + 1, probes=[(n, c) for n in nets])
+        assert int(prof[c]) == int(ref["ig_cycle"][0]), c
+        for n, pr in zip(nets, ref["probes"]):
+            assert waves[(n, c)] == pr, (n, c)
+
+
 def test_scale_config_sample(G):
-    """The 1M-gate workload in the benchmark's launch configuration
-    (1,000-cycle windows from cycle 0, default tile and staging).  The GPU
-    runs cycles [0, 990) and [0, 1010); under cycle isolation their SAIF
-    difference is cycles 990..1009, which straddle the first window boundary
-    and are compared net by net with the oracle, plus a waveform sample from
-    the resident second window and the per-cycle glitch profile of those
-    cycles."""
+    """The 1M-gate workload in 1,000-cycle windows from cycle 0 (default tile
+    and staging).  The GPU runs cycles [0, 990) and [0, 1010); under cycle
+    isolation their SAIF difference is cycles 990..1009, which straddle the
+    first window boundary and are compared net by net with the oracle, plus
+    a waveform sample from the resident second window and the per-cycle
+    glitch profile of those cycles."""
     w = synth.scale(n_cycles=1100)
     b, e = 990, 1010
     N = 20_000 + 1_000_000
