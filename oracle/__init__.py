@@ -50,7 +50,7 @@ def _load():
     lib.oracle_level.restype = C.c_int32
     lib.oracle_run.restype = C.c_int32
     lib.oracle_run.argtypes = [P, C.c_int32, C.c_int32, P, P, P, C.c_int32, C.c_int32,
-                               P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_int32, P]
+                               P, P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_int32, P]
     _lib = lib
     return lib
 
@@ -118,8 +118,10 @@ class Oracle:
         Returns a dict with int64 arrays tc, t0, t1 and ig (glitch toggles; one
         entry per net: inputs first, then gate g's output as net n_inputs + g),
         ig_cycle (glitch toggles over all nets, one entry per cycle of the
-        range), event and edge counts, and — for each (net, cycle) probe —
-        (initial value, [times]).
+        range), late_cycle (per cycle, the nets whose last edge or its
+        arrival through a fanout wire reaches the period: 0 means the cycle
+        ends quiescent), event and edge counts, and — for each (net, cycle)
+        probe — (initial value, [times]).
 
         segment_cycles S > 1: each group of S consecutive cycles (from cycle
         0; n_cycles must be a multiple of S) is one continuous run from the
@@ -144,6 +146,7 @@ class Oracle:
         t1 = np.zeros(N, dtype=np.int64)
         ig = np.zeros(N, dtype=np.int64)
         ig_cycle = np.zeros(max(0, cycle_end - cycle_begin) + 1, dtype=np.int64)
+        late_cycle = np.zeros(max(0, cycle_end - cycle_begin) + 1, dtype=np.int64)
         init = np.ascontiguousarray(stim["init"], dtype=np.uint8)
         tp = np.ascontiguousarray(stim["toggle_ptr"], dtype=np.int64)
         ts = np.ascontiguousarray(stim["toggle_ps"], dtype=np.int64)
@@ -157,7 +160,7 @@ class Oracle:
         pt = np.zeros(max(npb, 1) * probe_cap, dtype=np.int32)
         stats = np.zeros(2, dtype=np.int64)
         rc = lib.oracle_run(self._h, int(stim["period"]), int(stim["n_cycles"]), _p(init), _p(tp), _p(ts),
-                            int(cycle_begin), int(cycle_end), _p(tc), _p(t0), _p(t1), _p(ig), _p(ig_cycle),
+                            int(cycle_begin), int(cycle_end), _p(tc), _p(t0), _p(t1), _p(ig), _p(ig_cycle), _p(late_cycle),
                             npb, _p(pn), _p(pc), _p(pi), _p(pl), _p(pt), probe_cap, _p(stats))
         if rc != 0:
             raise OracleError("oracle internal inconsistency")
@@ -165,7 +168,8 @@ class Oracle:
         for i in range(npb):
             ln = int(pl[i])
             out.append((int(pi[i]), pt[i * probe_cap: i * probe_cap + min(ln, probe_cap)].tolist(), ln))
-        return {"tc": tc, "t0": t0, "t1": t1, "ig": ig, "ig_cycle": ig_cycle[:max(0, cycle_end - cycle_begin)],
+        nc = max(0, cycle_end - cycle_begin)
+        return {"tc": tc, "t0": t0, "t1": t1, "ig": ig, "ig_cycle": ig_cycle[:nc], "late_cycle": late_cycle[:nc],
                 "events": int(stats[0]), "edges": int(stats[1]),
                 "probes": out}
 

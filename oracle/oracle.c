@@ -350,6 +350,15 @@ static int32_t pin_state(const Design *d, const int32_t *pin_val, int32_t g)
  * nets per cycle: the cycle-by-cycle glitch profile whose peaks are the
  * hot spots the glitch-optimization flow of Section 4 looks for.
  *
+ * late_cycle (may be NULL, length cycle_end - cycle_begin) counts, per
+ * cycle, the nets whose last edge in the cycle, or that edge's arrival at
+ * one of the net's fanout pins through the pin's wire delay (rise or fall
+ * by the value after the edge), lies at or after the period T.  A cycle
+ * whose count is 0 ends quiescent: every net holds the zero-delay value of
+ * the inputs and nothing is pending, so the next cycle's isolated start
+ * (the settled values) is exactly the state a continuous run would reach.
+ * The test is conservative: such an arrival may still be filtered.
+ *
  * Probes: for probe p, if cycle_begin <= probe_cycle[p] < cycle_end, the
  * initial value, edge count and up to probe_cap edge times of net
  * probe_net[p] in that cycle are written to probe_init[p], probe_len[p] and
@@ -362,7 +371,7 @@ int32_t oracle_run(void *p, int32_t period, int32_t n_cycles,
                    const uint8_t *init, const int64_t *toggle_ptr, const int64_t *toggle_ps,
                    int32_t cycle_begin, int32_t cycle_end,
                    int64_t *tc, int64_t *t0, int64_t *t1, int64_t *ig, int64_t *ig_cycle,
-                   int32_t n_probe, const int32_t *probe_net, const int32_t *probe_cycle,
+                   int64_t *late_cycle, int32_t n_probe, const int32_t *probe_net, const int32_t *probe_cycle,
                    int32_t *probe_init, int32_t *probe_len, int32_t *probe_times, int32_t probe_cap,
                    int64_t *stats)
 {
@@ -513,6 +522,16 @@ int32_t oracle_run(void *p, int32_t period, int32_t n_cycles,
             tc[n] += b - a;
             if (ig) ig[n] += (b - a) - ((b - a) & 1);
             if (ig_cycle) ig_cycle[c - cycle_begin] += (b - a) - ((b - a) & 1);
+            if (late_cycle && b > a) {
+                int64_t last = rec_t[ord[b - 1]], reach = last;
+                int32_t v_end = start_val[n] ^ (int32_t)((b - a) & 1);
+                for (int64_t k = d->fo_ptr[n]; k < d->fo_ptr[n + 1]; k++) {
+                    int32_t s = d->fo_slot[k];
+                    int64_t r = last + (v_end ? d->wire_r[s] : d->wire_f[s]);
+                    if (r > reach) reach = r;
+                }
+                if (reach >= T) late_cycle[c - cycle_begin]++;
+            }
             /* time at 1 and time at 0 in [0, T), summed segment by segment */
             int32_t v = start_val[n];
             int64_t prev = 0, on = 0, off = 0;

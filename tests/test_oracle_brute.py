@@ -58,6 +58,22 @@ def test_oracle_matches_brute(mode):
             ig_cycle[c] += len(times) - len(times) % 2
         assert r["ig"].tolist() == ig, seed
         assert r["ig_cycle"].tolist() == ig_cycle, seed
+        # late nets from the brute model's lists: the last edge, or its arrival
+        # through a fanout wire, reaches the period
+        T = int(w["stimulus"]["period"])
+        fn = w["netlist"]["fanin_net"]
+        wires = w.get("wires")
+        late = [0] * C
+        for (n, c), (init, times) in waves.items():
+            if not times:
+                continue
+            v_end = init ^ (len(times) & 1)
+            reach = times[-1]
+            if wires is not None:
+                for s_ in np.nonzero(fn == n)[0]:
+                    reach = max(reach, times[-1] + int((wires["rise"] if v_end else wires["fall"])[s_]))
+            late[c] += reach >= T
+        assert r["late_cycle"].tolist() == late, seed
         n_ok += 1
     assert n_ok == 120
 
@@ -162,6 +178,29 @@ def test_segments_match_brute(S):
         iso = oracle.simulate(w)
         n_diff += not (np.array_equal(iso["tc"], r["tc"]) and np.array_equal(iso["t1"], r["t1"]))
     assert n_diff >= 10
+
+
+def test_quiescent_cycles_certify_isolation():
+    """When no cycle but the last has a late net, the cycle-by-cycle run
+    equals one continuous run over all cycles, net by net; seeds of both
+    kinds occur."""
+    settled = unsettled = 0
+    for seed in range(3000, 3080):
+        rng = np.random.default_rng(seed)
+        T = int(rng.integers(8, 60))
+        G = int(rng.integers(2, 12))
+        w = synth.small_random(seed, G, 4, min(G, int(rng.integers(1, 4))), 4, T, 0.5, 1, 8,
+                               cond_frac=0.3, wire=(1, 5) if seed % 2 else None, extra=1, extra_p=0.3,
+                               skew=T // 3, edge_frac=0.3)
+        iso = oracle.simulate(w)
+        if iso["late_cycle"][:-1].sum() == 0:
+            settled += 1
+            cont = oracle.simulate(w, segment_cycles=4)
+            for k in ("tc", "t0", "t1"):
+                assert np.array_equal(iso[k], cont[k]), (seed, k)
+        else:
+            unsettled += 1
+    assert settled >= 10 and unsettled >= 10, (settled, unsettled)
 
 
 def test_cycle_isolation_matches_continuous_run():

@@ -282,6 +282,19 @@ def test_continuous_segments():
         oracle.simulate(w, segment_cycles=3)
 
 
+def test_late_lanes():
+    """A cycle ends quiescent unless a net's last edge, or its arrival at a
+    fanout pin through the pin's wire, reaches the period."""
+    w = work(1, [("BUF", [0])], (150, 150), [[20]], [0], period=100)
+    assert oracle.simulate(w)["late_cycle"].tolist() == [1]          # the output edge at 170
+    w = work(1, [("BUF", [0])], (50, 50), [[20]], [0], period=100)
+    assert oracle.simulate(w)["late_cycle"].tolist() == [0]          # edge at 70
+    w = work(1, [("BUF", [0])], (5, 5), [[20]], [0], period=100, wires=[(90, 60)])
+    assert oracle.simulate(w)["late_cycle"].tolist() == [2]          # arrival 110, output edge 115
+    w = work(1, [("BUF", [0])], (5, 5), [[20, 30]], [0], period=100, wires=[(90, 60)])
+    assert oracle.simulate(w)["late_cycle"].tolist() == [0]          # the falling edge arrives at 90
+
+
 def test_cycles_are_isolated():
     """Each cycle starts from the settled values; an edge later than the
     period still belongs to its cycle and is clipped out of T0/T1."""
