@@ -176,6 +176,26 @@ gs_status gs_load_stimulus(gs_ctx *ctx, int32_t design, int32_t period_ps, int32
 gs_status gs_glitch_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end,
                             int64_t *per_cycle);
 
+/* Per-cycle profile with a check of the cycle-isolated reading (Section 1
+ * breaks the cycle dependency with known waveforms; that is exact where
+ * logic settles within a period): re-simulates [cycle_begin, cycle_end) as
+ * gs_simulate does (adding the SAIF counts) and writes, for every cycle c of
+ * the range at index c - cycle_begin,
+ *   glitch[]: the glitch toggles of cycle c over all nets (gs_glitch_profile);
+ *   late[]:   the nets whose last edge in cycle c, or that edge's arrival at
+ *             a fanout pin through the net's slowest wire for the edge's
+ *             direction, lies at or after the period.
+ * A cycle with no late net ends quiescent, so the next cycle's isolated
+ * start is exactly the state a continuous run reaches: when no cycle but
+ * the last of a range has a late net, the range's cycle-by-cycle result
+ * equals one continuous run over it.  The test is conservative (such an
+ * arrival may still be filtered out).  On a segment view, cycles are
+ * segments.  Either array may be NULL; both are caller-owned host arrays of
+ * cycle_end - cycle_begin entries.  The late count reads one extra word per
+ * (net, cycle) that has edges.  Errors: as gs_simulate. */
+gs_status gs_cycle_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end,
+                           int64_t *glitch, int64_t *late);
+
 /* Continuous segments (the re-simulation of Section 1 without isolating
  * every cycle): creates a view of stimulus `stim` in which each group of
  * segment_cycles consecutive cycles, from cycle 0, is one cycle.  Every call

@@ -126,8 +126,11 @@ struct gs_ctx {
     hipStream_t cap_stream = nullptr;        // library stream that graphs are captured on and launched from
     int32_t *d_c0 = nullptr;                 // first cycle of every piece of the running round
     size_t c0_cap = 0;
-    unsigned long long *d_profile = nullptr; // set while gs_glitch_profile runs: per-cycle totals
-    int32_t profile_begin = 0;               // the cycle of d_profile[0]
+    // set while gs_cycle_profile runs: per-cycle totals (either may be null)
+    unsigned long long *d_profile = nullptr; // glitch toggles
+    unsigned long long *d_late = nullptr;    // late nets
+    const int32_t *d_wout = nullptr;         // per net: slowest fanout wire, rise and fall (null: no wires)
+    int32_t profile_begin = 0;               // the cycle of entry 0
     std::map<std::string, std::array<int32_t, 3>> tuned;   // autotuned (cap, wpb, tpw) per batch shape
     // serving
     ServeState *serve = nullptr;

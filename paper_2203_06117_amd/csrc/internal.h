@@ -160,9 +160,13 @@ hipError_t launch_edit_apply(const EditRec *ed, uint32_t n, const int32_t *slot,
                              uint32_t n_cone, hipStream_t s);
 // Zeroes the SAIF counters of the output nets of gates[0 .. n).
 // Adds, for every cycle of a finished window, the glitch toggles of nets
-// [0, n_nets) (edge count less its parity) into out[cycle].
-hipError_t launch_glitch_profile(const uint16_t *ends, uint32_t n_nets, uint32_t tiles, uint32_t cycles,
-                                 unsigned long long *out, hipStream_t s);
+// [0, n_nets) (edge count less its parity) into glitch[cycle] and, when late
+// is not null, the nets whose last edge, or its arrival through the net's
+// slowest fanout wire (wout: rise and fall maximum per net, null = none),
+// reaches the period into late[cycle].  glitch may be null.
+hipError_t launch_cycle_profile(const uint16_t *ends, const ChunkHdr *hdr, const int32_t *times, const int32_t *wout,
+                                uint32_t n_nets, uint32_t tiles, uint32_t cycles, int32_t period,
+                                unsigned long long *glitch, unsigned long long *late, hipStream_t s);
 hipError_t launch_saif_zero(const GateRec *gates, uint32_t n, SaifAcc acc, hipStream_t s);
 
 }  // namespace gs

@@ -1222,18 +1222,28 @@ hipError_t launch_cone_place(const GateRec *gates, const PinRec *pins, uint32_t 
     return hipGetLastError();
 }
 
-// Per-cycle glitch profile of a finished window.  One wave per (64-cycle
-// tile, group of kProfileNets nets), lane = cycle, tiles fastest so that
-// neighbouring waves read neighbouring lines of a net; a lane's edge count
-// is its inclusive end less its left neighbour's.  One atomic add per lane.
+// Per-cycle profile of a finished window: glitch toggles (a lane's edge
+// count less its parity) and late nets (the lane's last edge, or its
+// arrival through the net's slowest fanout wire for that edge's direction,
+// at or after the period), each summed over nets [0, n_nets) per cycle.
+// One wave per (64-cycle tile, group of kProfileNets nets), lane = cycle,
+// tiles fastest so that neighbouring waves read neighbouring lines of a
+// net; a lane's edge count is its inclusive end less its left neighbour's.
 // The difference is written as an addition of the shifted negation: a
 // subtraction would be fused with the lane shift into a reversed-operand
-// form, which gave the negated count on this chip.
+// form, which gave the negated count on this chip.  One atomic add per
+// lane and output.  LATE: also read each lane's last edge (wout: rise and
+// fall fanout wire maximum per net, or null for none).
 constexpr uint32_t kProfileNets = 2048;
 
-__global__ __launch_bounds__(256) void glitch_profile_kernel(const uint16_t *__restrict__ ends, uint32_t n_nets,
-                                                             uint32_t tiles, uint32_t cycles,
-                                                             unsigned long long *__restrict__ out, uint64_t n_waves)
+template <bool LATE>
+__global__ __launch_bounds__(256) void cycle_profile_kernel(const uint16_t *__restrict__ ends,
+                                                            const ChunkHdr *__restrict__ hdr,
+                                                            const int32_t *__restrict__ times,
+                                                            const int32_t *__restrict__ wout, uint32_t n_nets,
+                                                            uint32_t tiles, uint32_t cycles, int32_t T,
+                                                            unsigned long long *__restrict__ glitch,
+                                                            unsigned long long *__restrict__ late, uint64_t n_waves)
 {
     const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + threadIdx.x / kLanes;
     if (w >= n_waves) return;                                   // whole waves leave together
@@ -1246,34 +1256,59 @@ __global__ __launch_bounds__(256) void glitch_profile_kernel(const uint16_t *__r
     const uint64_t stride = (uint64_t)tiles * kLanes;
     const uint16_t *p = ends + ((uint64_t)n0 * tiles + tile) * kLanes;
     uint32_t acc = 0;                                           // at most kProfileNets x kMaxChunk
+    uint32_t nlate = 0;
     uint32_t n = n0;
     for (; n + 8 <= n1; n += 8, p += 8 * stride) {
         uint32_t e[8];
 #pragma unroll
-        for (int u = 0; u < 8; u++) e[u] = ld_u16(p + u * stride, lane) & kEndCount;
+        for (int u = 0; u < 8; u++) e[u] = ld_u16(p + u * stride, lane);
 #pragma unroll
         for (int u = 0; u < 8; u++) {
-            const uint32_t c = e[u] + wave_shr1(0u - e[u]);
+            const uint32_t x = e[u] & kEndCount;
+            const uint32_t c = x + wave_shr1(0u - x);
             acc += c - (c & 1u);
+            if (LATE && c) {
+                const ChunkHdr h = *kons(hdr + (uint64_t)(n + u) * tiles + tile);
+                const int32_t last = ld_word(times + h.off, x - 1u);
+                const uint32_t v_end = ((e[u] >> kEndInitShift) & 1u) ^ (c & 1u);
+                const int32_t wd = wout ? *kons(wout + 2 * (uint64_t)(n + u) + (v_end ? 0 : 1)) : 0;
+                nlate += (last + wd >= T) ? 1u : 0u;
+            }
         }
     }
     for (; n < n1; n++, p += stride) {
-        const uint32_t e = ld_u16(p, lane) & kEndCount;
-        const uint32_t c = e + wave_shr1(0u - e);
+        const uint32_t e = ld_u16(p, lane);
+        const uint32_t x = e & kEndCount;
+        const uint32_t c = x + wave_shr1(0u - x);
         acc += c - (c & 1u);
+        if (LATE && c) {
+            const ChunkHdr h = *kons(hdr + (uint64_t)n * tiles + tile);
+            const int32_t last = ld_word(times + h.off, x - 1u);
+            const uint32_t v_end = ((e >> kEndInitShift) & 1u) ^ (c & 1u);
+            const int32_t wd = wout ? *kons(wout + 2 * (uint64_t)n + (v_end ? 0 : 1)) : 0;
+            nlate += (last + wd >= T) ? 1u : 0u;
+        }
     }
     const uint32_t cyc = tile * kLanes + lane;
-    if (cyc < cycles && acc)
-        __hip_atomic_fetch_add(glob(out + cyc), (unsigned long long)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cyc < cycles && glitch && acc)
+        __hip_atomic_fetch_add(glob(glitch + cyc), (unsigned long long)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (LATE && cyc < cycles && nlate)
+        __hip_atomic_fetch_add(glob(late + cyc), (unsigned long long)nlate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-hipError_t launch_glitch_profile(const uint16_t *ends, uint32_t n_nets, uint32_t tiles, uint32_t cycles,
-                                 unsigned long long *out, hipStream_t s)
+hipError_t launch_cycle_profile(const uint16_t *ends, const ChunkHdr *hdr, const int32_t *times, const int32_t *wout,
+                                uint32_t n_nets, uint32_t tiles, uint32_t cycles, int32_t period,
+                                unsigned long long *glitch, unsigned long long *late, hipStream_t s)
 {
     if (n_nets == 0 || tiles == 0) return hipSuccess;
     const uint64_t n_waves = (uint64_t)((n_nets + kProfileNets - 1) / kProfileNets) * tiles;
-    hipLaunchKernelGGL(glitch_profile_kernel, dim3((unsigned)((n_waves + 3) / 4)), dim3(256), 0, s, ends, n_nets, tiles,
-                       cycles, out, n_waves);
+    const dim3 grid((unsigned)((n_waves + 3) / 4)), block(256);
+    if (late)
+        hipLaunchKernelGGL(cycle_profile_kernel<true>, grid, block, 0, s, ends, hdr, times, wout, n_nets, tiles, cycles,
+                           period, glitch, late, n_waves);
+    else
+        hipLaunchKernelGGL(cycle_profile_kernel<false>, grid, block, 0, s, ends, hdr, times, wout, n_nets, tiles,
+                           cycles, period, glitch, late, n_waves);
     return hipGetLastError();
 }
 

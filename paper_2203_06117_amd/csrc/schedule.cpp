@@ -282,10 +282,14 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
         ctx->stats.window_retries++;
         return GS_OK;
     }
-    if (ctx->d_profile)
-        for (const Piece &p : pieces)
-            HIPCHK(launch_glitch_profile(ctx->win.ends + p.chunk_base * kLanes, (uint32_t)p.d->N, (uint32_t)p.tiles,
-                                         (uint32_t)p.cycles, ctx->d_profile + (p.c0 - ctx->profile_begin), hs));
+    if (ctx->d_profile || ctx->d_late)
+        for (const Piece &p : pieces) {
+            const int64_t at = p.c0 - ctx->profile_begin;
+            HIPCHK(launch_cycle_profile(ctx->win.ends + p.chunk_base * kLanes, ctx->win.hdr + p.chunk_base,
+                                        ctx->win.times, ctx->d_wout, (uint32_t)p.d->N, (uint32_t)p.tiles,
+                                        (uint32_t)p.cycles, p.s->period, ctx->d_profile ? ctx->d_profile + at : nullptr,
+                                        ctx->d_late ? ctx->d_late + at : nullptr, hs));
+        }
     ctx->stats.gate_eval_ms += res.gate_eval_ms;
     ctx->stats.expand_ms += res.expand_ms;
     ctx->stats.gate_eval_launches += res.launches;
@@ -420,39 +424,71 @@ void gs_graph_cache_clear(gs_ctx *ctx)
     ctx->graphs.clear();
 }
 
-extern "C" gs_status gs_glitch_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin,
-                                      int32_t cycle_end, int64_t *per_cycle)
+extern "C" gs_status gs_cycle_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end,
+                                     int64_t *glitch, int64_t *late)
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
     if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
     gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
     if (st) return st;
     const int32_t n = cycle_end - cycle_begin;
-    if (n > 0 && !per_cycle) return gs_fail(ctx, GS_E_INVALID, "null per_cycle");
     (void)hipSetDevice(ctx->opt.device);
-    unsigned long long *prof = nullptr;
-    if (hipMalloc((void **)&prof, sizeof(unsigned long long) * std::max(n, 1)) != hipSuccess) {
-        (void)hipGetLastError();
-        return gs_fail(ctx, GS_E_NOMEM, "cannot allocate the glitch profile");
+    const Design *d = ctx->designs[design];
+    // per net: the slowest fanout wire for a rising and for a falling edge
+    std::vector<int32_t> wout;
+    if (late && d->has_wires) {
+        wout.assign(2 * (size_t)d->N, 0);
+        for (int64_t s = 0; s < d->F; s++) {
+            const size_t net = (size_t)d->fanin_net[s];
+            wout[2 * net] = std::max(wout[2 * net], d->wr[s]);
+            wout[2 * net + 1] = std::max(wout[2 * net + 1], d->wf[s]);
+        }
     }
-    hipError_t he = launch_fill_u64(prof, (uint64_t)std::max(n, 1), 0ull, ctx->stream);
+    const size_t m = (size_t)std::max(n, 1);
+    unsigned long long *buf = nullptr;
+    int32_t *dw = nullptr;
+    if (hipMalloc((void **)&buf, sizeof(unsigned long long) * 2 * m) != hipSuccess ||
+        (!wout.empty() && hipMalloc((void **)&dw, sizeof(int32_t) * wout.size()) != hipSuccess)) {
+        (void)hipGetLastError();
+        gs_dev_free(buf);
+        return gs_fail(ctx, GS_E_NOMEM, "cannot allocate the cycle profile");
+    }
+    hipError_t he = launch_fill_u64(buf, 2 * m, 0ull, ctx->stream);
+    if (he == hipSuccess && dw)
+        he = hipMemcpyAsync(dw, wout.data(), sizeof(int32_t) * wout.size(), hipMemcpyHostToDevice, ctx->stream);
     if (he != hipSuccess) {
-        gs_dev_free(prof);
+        gs_dev_free(buf);
+        gs_dev_free(dw);
         return gs_fail(ctx, GS_E_DEVICE, "%s", hipGetErrorString(he));
     }
-    ctx->d_profile = prof;
+    ctx->d_profile = glitch ? buf : nullptr;
+    ctx->d_late = late ? buf + m : nullptr;
+    ctx->d_wout = dw;
     ctx->profile_begin = cycle_begin;
     st = gs_simulate(ctx, design, stim, cycle_begin, cycle_end);
     ctx->d_profile = nullptr;
-    std::vector<unsigned long long> h((size_t)std::max(n, 1));
-    if (!st && (hipMemcpyAsync(h.data(), prof, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+    ctx->d_late = nullptr;
+    ctx->d_wout = nullptr;
+    std::vector<unsigned long long> h(2 * m);
+    if (!st && (hipMemcpyAsync(h.data(), buf, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
                                ctx->stream) != hipSuccess ||
                 hipStreamSynchronize(ctx->stream) != hipSuccess))
-        st = gs_fail(ctx, GS_E_DEVICE, "glitch profile readback failed");
-    gs_dev_free(prof);
+        st = gs_fail(ctx, GS_E_DEVICE, "cycle profile readback failed");
+    gs_dev_free(buf);
+    gs_dev_free(dw);
     if (st) return st;
-    for (int32_t c = 0; c < n; c++) per_cycle[c] = (int64_t)h[c];
+    for (int32_t c = 0; c < n; c++) {
+        if (glitch) glitch[c] = (int64_t)h[c];
+        if (late) late[c] = (int64_t)h[m + c];
+    }
     return GS_OK;
+}
+
+extern "C" gs_status gs_glitch_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin,
+                                      int32_t cycle_end, int64_t *per_cycle)
+{
+    if (ctx && cycle_end > cycle_begin && !per_cycle) return gs_fail(ctx, GS_E_INVALID, "null per_cycle");
+    return gs_cycle_profile(ctx, design, stim, cycle_begin, cycle_end, per_cycle, nullptr);
 }
 
 extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end)

@@ -99,6 +99,7 @@ _SIGS = {
     "gs_load_stimulus": (I32, [P, I32, I32, I32, P, P, P, C.POINTER(I32)]),
     "gs_segment_stimulus": (I32, [P, I32, I32, C.POINTER(I32)]),
     "gs_glitch_profile": (I32, [P, I32, I32, I32, I32, P]),
+    "gs_cycle_profile": (I32, [P, I32, I32, I32, I32, P, P]),
     "gs_simulate": (I32, [P, I32, I32, I32, I32]),
     "gs_read_saif": (I32, [P, I32, P, P, P, I32]),
     "gs_read_saif_ig": (I32, [P, I32, P, P, P, P, I32]),
@@ -265,6 +266,18 @@ class GateSim:
         out = np.zeros(max(0, int(cycle_end) - int(cycle_begin)), dtype=np.int64)
         self._chk(_lib.gs_glitch_profile(self._h, int(design), int(stim), int(cycle_begin), int(cycle_end), _p(out)))
         return out
+
+    def cycle_profile(self, design, stim, cycle_begin, cycle_end):
+        """Simulates like ``simulate``; returns (glitch, late) per cycle of the
+        range: glitch toggles over all nets, and nets whose activity reaches
+        the end of the cycle (0 everywhere but the last cycle certifies that
+        the cycle-by-cycle result equals a continuous run)."""
+        n = max(0, int(cycle_end) - int(cycle_begin))
+        glitch = np.zeros(n, dtype=np.int64)
+        late = np.zeros(n, dtype=np.int64)
+        self._chk(_lib.gs_cycle_profile(self._h, int(design), int(stim), int(cycle_begin), int(cycle_end),
+                                        _p(glitch), _p(late)))
+        return glitch, late
 
     def segment_stimulus(self, stim, segment_cycles) -> int:
         """A view of ``stim`` whose cycles are groups of ``segment_cycles``

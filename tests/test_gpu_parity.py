@@ -175,6 +175,39 @@ def test_glitch_profile(G, opt):
             assert np.array_equal(prof, oracle.simulate(w, 2, 60, segment_cycles=5)["ig_cycle"])
 
 
+@pytest.mark.parametrize("opt", [dict(), dict(window_cycles=37, tiles_per_wave=3)])
+def test_late_nets(G, opt):
+    """Per-cycle counts of nets whose activity reaches the end of the cycle,
+    with the glitch totals, against the oracle: short periods (most cycles
+    late), long ones (none), with and without wires, and on a segment view;
+    where no cycle but the last is late, the run equals a continuous one."""
+    for seed, T, wire in ((11, 120, None), (12, 150, (1, 30)), (13, 4000, None), (14, 4000, (1, 30))):
+        w = synth.small_random(seed + 8200, 800, 24, 20, 140, T, 0.3, 2, 60, cond_frac=0.2, wire=wire,
+                               extra=1 if T < 1000 else 0, extra_p=0.3, skew=min(50, T - 1), edge_frac=0.2)
+        ref = oracle.simulate(w, 3, 131)
+        say("late", seed, T, wire, opt)
+        with G.GateSim(**opt) as sim:
+            d, s = sim.load_work(w)
+            glitch, late = sim.cycle_profile(d, s, 3, 131)
+            tc, t0, t1, ig = sim.read_saif_ig(d, reset=True)
+            assert np.array_equal(late, ref["late_cycle"]), (seed, np.nonzero(late != ref["late_cycle"])[0][:5])
+            assert np.array_equal(glitch, ref["ig_cycle"]), seed
+            assert_same(w, (tc, t0, t1, [], {}, ig), ref, f"late {seed}")
+            if T < 1000:
+                assert late.sum() > 0
+            else:
+                assert late[:-1].sum() == 0
+                cont = oracle.simulate(w, segment_cycles=140)
+                full = oracle.simulate(w)
+                for k in ("tc", "t0", "t1"):
+                    assert np.array_equal(full[k], cont[k]), k
+            if not opt and seed == 12:
+                v = sim.segment_stimulus(s, 7)
+                glitch, late = sim.cycle_profile(d, v, 0, 20)
+                r7 = oracle.simulate(w, 0, 20, segment_cycles=7)
+                assert np.array_equal(late, r7["late_cycle"]) and np.array_equal(glitch, r7["ig_cycle"])
+
+
 def test_tiny_config_waveforms(G):
     """2,000 gates x 100 cycles: all SAIF counts plus a sample of full
     waveforms (the analog of the paper's spot-checks)."""
@@ -372,8 +405,8 @@ def test_scale_bench_launch(G):
     """The 1M-gate workload exactly as the benchmark launches it: all 10,000
     cycles in one window, default tiles, staging and options.  Ten cycles
     spread over the run are re-simulated by the oracle; the GPU's waveforms
-    of 60 nets in each and its per-cycle glitch totals must equal the
-    oracle's, and T0 + T1 = C x T for every net."""
+    of 60 nets in each and its per-cycle glitch and late-net totals must
+    equal the oracle's, and T0 + T1 = C x T for every net."""
     w = synth.scale()
     C, T = w["stimulus"]["n_cycles"], w["stimulus"]["period"]
     N = 20_000 + 1_000_000
@@ -383,7 +416,7 @@ def test_scale_bench_launch(G):
     say("scale launch: gpu")
     with G.GateSim() as sim:
         d, s = sim.load_work(w)
-        prof = sim.glitch_profile(d, s, 0, C)
+        prof, late = sim.cycle_profile(d, s, 0, C)
         tc, t0, t1 = sim.read_saif(d)
         waves = {(n, c): sim.read_waveform(d, s, n, c) for c in cycles for n in nets}
     assert np.all(t0 + t1 == C * T)
@@ -392,6 +425,7 @@ def test_scale_bench_launch(G):
         say("scale launch: oracle cycle", c)
         ref = o.run(w["stimulus"], c, c + 1, probes=[(n, c) for n in nets])
         assert int(prof[c]) == int(ref["ig_cycle"][0]), c
+        assert int(late[c]) == int(ref["late_cycle"][0]), c
         for n, pr in zip(nets, ref["probes"]):
             assert waves[(n, c)] == pr, (n, c)
 
