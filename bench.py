@@ -363,13 +363,26 @@ def run_features(args, torch, synth, G):
         torch.cuda.synchronize()
         wall[name] = (time.perf_counter() - t) / 3 * 1e3
     prof = sim.glitch_profile(d, s, 0, cycles)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        _, late = sim.cycle_profile(d, s, 0, cycles)
+    torch.cuda.synchronize()
+    wall["cycle_profile"] = (time.perf_counter() - t) / 3 * 1e3
     sim.close()
-    log(f"features: simulate {wall['simulate']:.2f} ms, with glitch profile {wall['glitch_profile']:.2f} ms "
-        f"(peak cycle {int(prof.argmax())}: {int(prof.max())} glitch toggles, mean {prof.mean():.0f})")
+    n_nets = net["n_gates"] + net["n_inputs"]
+    late_share = float(late[:-1].sum()) / (n_nets * (cycles - 1))
+    log(f"features: simulate {wall['simulate']:.2f} ms, with glitch profile {wall['glitch_profile']:.2f} ms, "
+        f"with glitch and late counts {wall['cycle_profile']:.2f} ms (peak cycle {int(prof.argmax())}: "
+        f"{int(prof.max())} glitch toggles, mean {prof.mean():.0f}; {late_share:.4f} of (net, cycle) lists reach "
+        f"the next cycle)")
     base = res["averaged_arcs"]
     return {"workload": f"scale-1M, {cycles} cycles", "unit": "gate-cycles/s (gate-eval time)", **res,
             "simulate_ms": round(wall["simulate"], 3), "glitch_profile_ms": round(wall["glitch_profile"], 3),
             "glitch_profile_overhead": round(wall["glitch_profile"] / wall["simulate"] - 1, 4),
+            "cycle_profile_ms": round(wall["cycle_profile"], 3),
+            "cycle_profile_overhead": round(wall["cycle_profile"] / wall["simulate"] - 1, 4),
+            "late_share": round(late_share, 6),
             "cond_overhead": round(base / res["cond_arcs"] - 1, 4),
             "cond_and_edge_overhead": round(base / res["cond_and_edge_arcs"] - 1, 4),
             "segments16_overhead": round(base / res["cond_arcs_segments16"] - 1, 4),
