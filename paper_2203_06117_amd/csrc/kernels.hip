@@ -1271,8 +1271,9 @@ __global__ __launch_bounds__(256) void cycle_profile_kernel(const uint16_t *__re
                 const ChunkHdr h = *kons(hdr + (uint64_t)(n + u) * tiles + tile);
                 const int32_t last = ld_word(times + h.off, x - 1u);
                 const uint32_t v_end = ((e[u] >> kEndInitShift) & 1u) ^ (c & 1u);
-                const int32_t wd = wout ? *kons(wout + 2 * (uint64_t)(n + u) + (v_end ? 0 : 1)) : 0;
-                nlate += (last + wd >= T) ? 1u : 0u;
+                const int32_t wr = wout ? *kons(wout + 2 * (uint64_t)(n + u)) : 0;
+                const int32_t wf = wout ? *kons(wout + 2 * (uint64_t)(n + u) + 1) : 0;
+                nlate += (last + (v_end ? wr : wf) >= T) ? 1u : 0u;
             }
         }
     }
@@ -1285,8 +1286,9 @@ __global__ __launch_bounds__(256) void cycle_profile_kernel(const uint16_t *__re
             const ChunkHdr h = *kons(hdr + (uint64_t)n * tiles + tile);
             const int32_t last = ld_word(times + h.off, x - 1u);
             const uint32_t v_end = ((e >> kEndInitShift) & 1u) ^ (c & 1u);
-            const int32_t wd = wout ? *kons(wout + 2 * (uint64_t)n + (v_end ? 0 : 1)) : 0;
-            nlate += (last + wd >= T) ? 1u : 0u;
+            const int32_t wr = wout ? *kons(wout + 2 * (uint64_t)n) : 0;
+            const int32_t wf = wout ? *kons(wout + 2 * (uint64_t)n + 1) : 0;
+            nlate += (last + (v_end ? wr : wf) >= T) ? 1u : 0u;
         }
     }
     const uint32_t cyc = tile * kLanes + lane;
