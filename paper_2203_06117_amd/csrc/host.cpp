@@ -253,9 +253,19 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
     }
     if (o.device < 0 || o.device >= ndev) return gs_fail(nullptr, GS_E_DEVICE, "device %d not present", o.device);
     if (hipSetDevice(o.device) != hipSuccess) return gs_fail(nullptr, GS_E_DEVICE, "hipSetDevice failed");
+    int lim = 0;
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, o.device) != hipSuccess || lim <= 0) {
+        (void)hipGetLastError();
+        lim = 65536;
+    }
+    if (!auto_cap && gate_eval_lds_bytes(o.lds_cap, o.waves_per_block) > (size_t)lim)
+        return gs_fail(nullptr, GS_E_INVALID, "lds_cap %d with %d waves per block needs %zu bytes of LDS per block; "
+                       "the device allows %d", o.lds_cap, o.waves_per_block,
+                       gate_eval_lds_bytes(o.lds_cap, o.waves_per_block), lim);
     gs_ctx *ctx = new gs_ctx();
     ctx->opt = o;
     ctx->auto_cap = auto_cap;
+    ctx->lds_limit = (size_t)lim;
     if (o.stream) {
         ctx->stream = (hipStream_t)o.stream;
         ctx->own_stream = false;

@@ -105,6 +105,7 @@ struct GraphEntry {
 struct gs_ctx {
     gs_options opt;
     bool auto_cap = false;                   // lds_cap left to the library: sized per round by tuning_for
+    size_t lds_limit = 65536;                // LDS bytes a block may use on the device
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;

@@ -16,6 +16,16 @@ constexpr uint32_t kMaxChunk = 32767;       // transitions per (net, 64-cycle ti
 constexpr uint32_t kEndCount = 0x7fffu;
 constexpr uint32_t kEndInitShift = 15;
 
+// Fanin words a gate-evaluation wave stages in LDS for one group of tiles.
+constexpr uint32_t kStageWords = 512;
+
+// LDS of one gate-evaluation block: per wave the delay table (64 words),
+// cap + 1 output slots per lane and the fanin stage.
+__host__ __device__ constexpr size_t gate_eval_lds_bytes(int cap, int wpb)
+{
+    return (size_t)wpb * ((size_t)(cap + 1) * kLanes + kLanes + kStageWords) * sizeof(int32_t);
+}
+
 // One gate in level order (the level partition of Section 3), 32 bytes.
 struct GateRec {
     uint32_t out;       // output net id

@@ -447,9 +447,6 @@ hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *c
 // --------------------------------------------------------------------------
 extern __shared__ int32_t gs_lds[];
 
-// Fanin words a wave stages in LDS for one group of tiles.
-constexpr uint32_t kStageWords = 512;
-
 // chunk[idx] with a 32-bit byte offset from a wave-uniform base, so the
 // load can use the scalar-base + vector-offset addressing mode
 __device__ __forceinline__ int32_t ld_word(const int32_t *chunk, uint32_t idx)
@@ -1091,7 +1088,7 @@ static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
                             hipStream_t s)
 {
     const uint64_t blocks = (n_waves + wpb - 1) / wpb;
-    const size_t lds = (size_t)wpb * ((size_t)(cap + 1) * kLanes + kLanes + kStageWords) * sizeof(int32_t);
+    const size_t lds = gate_eval_lds_bytes(cap, wpb);
     const dim3 grid((unsigned)blocks), block(kLanes * wpb);
     switch (cap) {
     case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;

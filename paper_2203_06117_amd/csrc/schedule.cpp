@@ -58,6 +58,7 @@ Tuning tuning_for(const gs_ctx *ctx, const std::vector<Piece> &ps)
         rho = std::max(rho, (double)tog / ((double)std::max(1, p.d->I) * std::max(1, p.cycles)));
     }
     t.cap = rho <= 0.5 ? 8 : rho <= 1.0 ? 16 : 32;
+    while (t.wpb > 1 && gate_eval_lds_bytes(t.cap, t.wpb) > ctx->lds_limit) t.wpb /= 2;   // fit the block's LDS
     return t;
 }
 
@@ -528,6 +529,7 @@ static gs_status autotune_impl(gs_ctx *ctx, const std::vector<Piece> &trial, Tun
     ctx->opt.schedule = GS_SCHED_LEVELS;              // events bracket every launch
     gs_stats saved = ctx->stats;
     for (const Tuning &t : cands) {
+        if (gate_eval_lds_bytes(t.cap, t.wpb) > ctx->lds_limit) continue;     // does not fit the device
         double ms = 0;
         gs_status st = run_pieces(ctx, trial, t, false, true, &ms);   // warm
         if (st) { ctx->opt.schedule = saved_sched; ctx->stats = saved; return st; }

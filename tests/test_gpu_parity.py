@@ -208,6 +208,56 @@ def test_late_nets(G, opt):
                 assert np.array_equal(late, r7["late_cycle"]) and np.array_equal(glitch, r7["ig_cycle"])
 
 
+def test_random_feature_mix(G):
+    """Forty small designs, each drawing its own mix of every feature
+    (conditional and input-edge-qualified arcs, wires, cells of up to six
+    pins, multi-edge inputs, continuous segments) and of launch options
+    (window, tiles per wave, staging cap, block shape, schedule); SAIF, glitch
+    toggles, the per-cycle profile and late counts all equal the oracle's."""
+    for case in range(40):
+        rng = np.random.default_rng(9000 + case)
+        wide = bool(rng.random() < 0.3)
+        gates = int(rng.integers(20, 600))
+        S = int(rng.choice([1, 1, 2, 3, 8]))
+        C = S * int(rng.integers(3, 90))
+        T = int(rng.integers(40, 900))
+        w = synth.small_random(9000 + case, gates, int(rng.integers(8, 30)), min(gates, int(rng.integers(2, 25))), C, T,
+                               float(rng.uniform(0.05, 0.6)), 1, int(rng.integers(2, 80)),
+                               cond_frac=float(rng.choice([0.0, 0.2, 0.5])),
+                               wire=(1, int(rng.integers(1, 30))) if rng.random() < 0.4 else None,
+                               extra=int(rng.choice([0, 0, 2])), extra_p=0.3, skew=min(50, T - 1), wide=wide,
+                               edge_frac=float(rng.choice([0.0, 0.3])))
+        opt = {}
+        if rng.random() < 0.5:
+            opt["window_cycles"] = int(rng.choice([17, 64, 100]))
+        if rng.random() < 0.5:
+            opt["tiles_per_wave"] = int(rng.choice([1, 2, 3, 8, 16]))
+        if rng.random() < 0.4:
+            opt["lds_cap"] = int(rng.choice([4, 8, 16, 32]))
+        if rng.random() < 0.3:
+            opt["waves_per_block"] = int(rng.choice([1, 2, 8]))
+            if opt["waves_per_block"] == 8 and opt.get("lds_cap") == 32:
+                opt["waves_per_block"] = 2          # 86 KB of LDS per block may exceed the device's limit
+        if rng.random() < 0.3:
+            opt["schedule"] = G.SCHED_GRAPH
+        n = C // S
+        b = int(rng.integers(0, n))
+        e = int(rng.integers(b + 1, n + 1))
+        say("mix", case, gates, C, T, S, wide, opt, (b, e))
+        ref = oracle.simulate(w, b, e, segment_cycles=S)
+        with G.GateSim(**opt) as sim:
+            if wide:
+                sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)
+            d, s = sim.load_work(w, cells_loaded=wide)
+            if S > 1:
+                s = sim.segment_stimulus(s, S)
+            glitch, late = sim.cycle_profile(d, s, b, e)
+            tc, t0, t1, ig = sim.read_saif_ig(d)
+        assert_same(w, (tc, t0, t1, [], {}, ig), ref, f"mix {case}")
+        assert np.array_equal(glitch, ref["ig_cycle"]), case
+        assert np.array_equal(late, ref["late_cycle"]), case
+
+
 def test_tiny_config_waveforms(G):
     """2,000 gates x 100 cycles: all SAIF counts plus a sample of full
     waveforms (the analog of the paper's spot-checks)."""
