@@ -507,8 +507,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU cycle sharding is a design "
-                                   "note only (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the simulator runs on one GPU; sharding cycle ranges over several GPUs "
+                                   "is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
