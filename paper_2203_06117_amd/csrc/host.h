@@ -61,6 +61,12 @@ struct Design {
     bool arcs_loaded = false, has_wires = false;
     int32_t zero_delay = 0, max_delay = 0, max_wire = 0;
     uint64_t version = 0;
+    // learned from earlier rounds, used for performance only: transition
+    // words per net and picosecond of lane time in the last round that ran
+    // this design alone (a segment view's lanes are longer), and the window
+    // length a full arena last forced (0 = none)
+    double words_per_ps = 0;
+    int32_t window_fit = 0;
     // device
     int64_t *d_fanin_ptr = nullptr;
     int32_t *d_fanin_net = nullptr;

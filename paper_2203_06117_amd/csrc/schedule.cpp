@@ -52,10 +52,13 @@ Tuning tuning_for(const gs_ctx *ctx, const std::vector<Piece> &ps)
 {
     Tuning t = current_tuning(ctx);
     if (!ctx->auto_cap) return t;
+    // inputs alone underrate designs whose logic multiplies glitches: take
+    // the transitions per (net, cycle) seen when the design last ran too
     double rho = 0;
     for (const Piece &p : ps) {
         const int64_t tog = p.s->tog_prefix[p.c0 + p.cycles] - p.s->tog_prefix[p.c0];
         rho = std::max(rho, (double)tog / ((double)std::max(1, p.d->I) * std::max(1, p.cycles)));
+        rho = std::max(rho, p.d->words_per_ps * (double)p.s->period);
     }
     t.cap = rho <= 0.5 ? 8 : rho <= 1.0 ? 16 : 32;
     while (t.wpb > 1 && gate_eval_lds_bytes(t.cap, t.wpb) > ctx->lds_limit) t.wpb /= 2;   // fit the block's LDS
@@ -291,6 +294,9 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
                                         (uint32_t)p.cycles, p.s->period, ctx->d_profile ? ctx->d_profile + at : nullptr,
                                         ctx->d_late ? ctx->d_late + at : nullptr, hs));
         }
+    if (pieces.size() == 1 && pieces[0].cycles > 0)       // learn the design's list density
+        pieces[0].d->words_per_ps = (double)used / ((double)std::max(1, pieces[0].d->N) * pieces[0].cycles *
+                                                    (double)pieces[0].s->period);
     ctx->stats.gate_eval_ms += res.gate_eval_ms;
     ctx->stats.expand_ms += res.expand_ms;
     ctx->stats.gate_eval_launches += res.launches;
@@ -309,7 +315,12 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
 
 uint64_t piece_arena_guess(const Piece &p)
 {
-    return gs_arena_guess(p.d->N, p.cycles, p.s->tog_prefix[p.c0 + p.cycles] - p.s->tog_prefix[p.c0]);
+    uint64_t g = gs_arena_guess(p.d->N, p.cycles, p.s->tog_prefix[p.c0 + p.cycles] - p.s->tog_prefix[p.c0]);
+    // a design that ran before: its observed density with 15% to spare
+    if (p.d->words_per_ps > 0)
+        g = std::max<uint64_t>(g, (uint64_t)(p.d->words_per_ps * (double)p.s->period * 1.15 * (double)p.d->N *
+                                             p.cycles) + (1ull << 20));
+    return g;
 }
 
 // Runs `pieces` as rounds that fit the budget.  A round whose arena fills up
@@ -368,6 +379,7 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
         } else if (round[0].cycles > kLanes) {
             Piece p = round[0], a = p, b = p;
             a.cycles = p.cycles / 2;
+            p.d->window_fit = a.cycles;                       // later calls start at this length
             a.tiles = (a.cycles + kLanes - 1) / kLanes;
             b.c0 = p.c0 + a.cycles;
             b.cycles = p.cycles - a.cycles;
@@ -401,6 +413,7 @@ int32_t default_window(gs_ctx *ctx, const Design *d)
     if (W <= 0) {
         W = 16384;
         while (W > kLanes && gs_header_bytes(d->N, W) * 3 > ctx->budget) W /= 2;
+        if (d->window_fit > 0) W = std::min(W, d->window_fit);    // a full arena forced this length before
     }
     return W;
 }
