@@ -1061,6 +1061,9 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     // table is never written by the launch, so its fields load with s_load
     // and need not be reloaded after the kernel's own stores
     const Seg sg = *kons(segs + si);
+    // a round whose arena or a chunk already overflowed is rerun or failed
+    // as a whole: its remaining waves skip their work
+    if ((*kons(sg.win.flags) | *kons(sg.win.flags + 1)) != 0u) return;
     const uint32_t local = (uint32_t)(w - sg.wave_begin);
     const uint32_t ntile = (uint32_t)sg.win.n_tiles;
     const uint32_t ngroup = (ntile + tpw - 1) / tpw;
