@@ -304,6 +304,27 @@ def test_dense_activity(G):
             assert got[4]["spilled_lanes"] > 0
 
 
+def test_learned_density(G):
+    """A design whose logic multiplies its inputs' toggles (ripple-carry-like
+    XOR/MUX chains, about 1.07 transitions per net and cycle from 0.3 input
+    toggles): the first run sizes the staging cap from the inputs, the second
+    from the density the first observed; both equal the oracle, and the
+    second re-walks fewer lanes."""
+    w = synth.glitchy(seed=21, n_gates=20000, n_inputs=400, n_levels=60, n_cycles=128)
+    ref = oracle.simulate(w)
+    spilled = []
+    with G.GateSim() as sim:
+        d, s = sim.load_work(w)
+        for run in range(2):
+            say("learned density, run", run)
+            sim.stats(reset=True)
+            sim.simulate(d, s, 0, 128)
+            spilled.append(sim.stats()["spilled_lanes"])
+            tc, t0, t1, ig = sim.read_saif_ig(d, reset=True)
+            assert_same(w, (tc, t0, t1, [], {}, ig), ref, f"run {run}")
+    assert spilled[1] < spilled[0], spilled
+
+
 @pytest.mark.parametrize("opt", [dict(), dict(tiles_per_wave=3), dict(lds_cap=4, waves_per_block=2)])
 def test_wide_cells(G, opt):
     """Cells of four to six pins (no delay lookup table; arc delays chosen per
