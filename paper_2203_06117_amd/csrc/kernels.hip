@@ -1262,18 +1262,28 @@ __global__ __launch_bounds__(256) void cycle_profile_kernel(const uint16_t *__re
         uint32_t e[8];
 #pragma unroll
         for (int u = 0; u < 8; u++) e[u] = ld_u16(p + u * stride, lane);
+        uint32_t c[8];
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             const uint32_t x = e[u] & kEndCount;
-            const uint32_t c = x + wave_shr1(0u - x);
-            acc += c - (c & 1u);
-            if (LATE && c) {
+            c[u] = x + wave_shr1(0u - x);
+            acc += c[u] - (c[u] & 1u);
+        }
+        if (LATE) {
+            // all eight last-edge reads go out before the first is used
+            int32_t last[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
                 const ChunkHdr h = *kons(hdr + (uint64_t)(n + u) * tiles + tile);
-                const int32_t last = ld_word(times + h.off, x - 1u);
-                const uint32_t v_end = ((e[u] >> kEndInitShift) & 1u) ^ (c & 1u);
+                last[u] = 0;
+                if (c[u]) last[u] = ld_word(times + h.off, (e[u] & kEndCount) - 1u);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const uint32_t v_end = ((e[u] >> kEndInitShift) & 1u) ^ (c[u] & 1u);
                 const int32_t wr = wout ? *kons(wout + 2 * (uint64_t)(n + u)) : 0;
                 const int32_t wf = wout ? *kons(wout + 2 * (uint64_t)(n + u) + 1) : 0;
-                nlate += (last + (v_end ? wr : wf) >= T) ? 1u : 0u;
+                nlate += (c[u] && last[u] + (v_end ? wr : wf) >= T) ? 1u : 0u;
             }
         }
     }
