@@ -38,12 +38,19 @@
  *    switching at the same time are applied together; the output edge takes
  *    the smallest of their arc delays, looked up in the pin state after the
  *    switch.
+ *  - Delay lookup (Algorithm 1's delay rows, indexed by input and output
+ *    edge; SDF conditional and posedge/negedge records): in each pin state
+ *    the most specific matching record applies (gs_arc).
  *  - Gate inertial filter with PATHPULSEPERCENT = 100 (Algorithm 1, output
  *    filter): when the output must change while its previous edge is still
  *    pending, the pending edge is cancelled; otherwise a new edge is
  *    scheduled after the arc delay.
  *  - SAIF (Section 3): TC = edges of the net, T1/T0 = time at 1/0, summed
- *    over the simulated cycles.
+ *    over the simulated cycles; IG = glitch toggles, a cycle's edges beyond
+ *    its one functional edge (gs_read_saif_ig).
+ *  - Optional: several cycles as one continuous segment
+ *    (gs_segment_stimulus); per-cycle glitch totals and a per-cycle check
+ *    of when the isolated model equals a continuous run (gs_cycle_profile).
  */
 #ifndef GATESIM_H
 #define GATESIM_H
