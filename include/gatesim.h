@@ -272,7 +272,10 @@ typedef struct {
     int64_t  arena_words;       /* 32-bit transition slots used by the last window */
     int64_t  graph_launches;    /* rounds replayed from a captured HIP graph */
     int64_t  unstaged_groups;   /* (gate, tile group) waves whose fanin words exceeded the on-chip stage */
-    int64_t  reserved[4];
+    int64_t  queue_overflows;   /* staged tile groups of gates with up to three pins that had more lanes with
+                                   two or more pin events than the compacted walk queues, and took the per-tile
+                                   walk instead */
+    int64_t  reserved[3];
 } gs_stats;
 
 gs_status gs_get_stats(gs_ctx *ctx, gs_stats *st, int32_t reset);

@@ -19,11 +19,29 @@ constexpr uint32_t kEndInitShift = 15;
 // Fanin words a gate-evaluation wave stages in LDS for one group of tiles.
 constexpr uint32_t kStageWords = 512;
 
-// LDS of one gate-evaluation block: per wave the delay table (64 words),
-// cap + 1 output slots per lane and the fanin stage.
+// Compacted evaluation of a staged tile group: a lane never has more output
+// edges than pin events, so the group's output edges fit a stage of the
+// same size; lanes with two or more pin events are queued (up to
+// kQueueCap of them, kQueueWords words each) and walked together.
+constexpr uint32_t kOutStageWords = kStageWords;
+constexpr uint32_t kQueueCap = 128;
+constexpr uint32_t kQueueWords = 4;
+
+// LDS words of one gate-evaluation wave: the delay table (64 words), the
+// fanin stage, then a region shared by the per-lane output slots of the
+// per-tile path (cap + 1 per lane) and the output stage plus lane queue of
+// the compacted path.
+__host__ __device__ constexpr size_t gate_eval_wave_words(int cap)
+{
+    return (size_t)kLanes + kStageWords +
+           ((size_t)(cap + 1) * kLanes > (size_t)kOutStageWords + kQueueCap * kQueueWords
+                ? (size_t)(cap + 1) * kLanes
+                : (size_t)kOutStageWords + kQueueCap * kQueueWords);
+}
+
 __host__ __device__ constexpr size_t gate_eval_lds_bytes(int cap, int wpb)
 {
-    return (size_t)wpb * ((size_t)(cap + 1) * kLanes + kLanes + kStageWords) * sizeof(int32_t);
+    return (size_t)wpb * gate_eval_wave_words(cap) * sizeof(int32_t);
 }
 
 // One gate in level order (the level partition of Section 3), 32 bytes.
@@ -69,7 +87,8 @@ struct WinView {
     int32_t *times;
     unsigned long long *bump;      // one counter per stripe, kBumpStride apart: words handed out in the stripe
     unsigned int *flags;           // [0] arena full, [1] chunk over kMaxChunk, [2] spilled lanes, [3] bound violated,
-                                   // [4] tile groups walked from the arena (too many words to stage)
+                                   // [4] tile groups walked from the arena (too many words to stage),
+                                   // [5] staged groups whose multi-event lanes overflowed the compacted queue
     uint64_t slice_words;          // arena words owned by each stripe
     uint64_t arena_off;            // first word of this window's arena, counted from `times`
     int32_t n_tiles;

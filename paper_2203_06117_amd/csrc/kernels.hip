@@ -730,6 +730,296 @@ __device__ __forceinline__ void walk_lds(Cursor<K, false, true> &P, const Arcs<K
     cnt_out = cnt;
 }
 
+// The event loop of walk_lds for a queued lane of the compacted path: the
+// lane's pin lists are staged at absolute LDS positions [idx, end), and its
+// output edges go to LDS slots opos, opos + 1, ...  A lane appends at most
+// one edge per event time, so the slot written in a step (the current count,
+// also when nothing is appended) stays below the lane's event count, inside
+// the region reserved for it.
+template <int K>
+__device__ __forceinline__ void walk_lds_c(Cursor<K, false, true> &P, int z, uint32_t lut_base, uint32_t opos,
+                                           int32_t &cnt_out)
+{
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+        const int32_t v = gs_lds[P.idx[j]];
+        P.a[j] = P.idx[j] < P.end[j] ? v : kInf;
+    }
+    int32_t W = 0, Wp = 0, cnt = 0;
+    for (;;) {
+        int32_t t = P.a[0];
+#pragma unroll
+        for (int j = 1; j < K; j++) t = min(t, P.a[j]);
+        if (t == kInf) break;
+        uint32_t sw = 0;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const uint32_t m = P.a[j] == t ? 1u : 0u;
+            sw |= m << j;
+            P.idx[j] += m;
+        }
+        P.state ^= sw;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const int32_t v = gs_lds[P.idx[j]];
+            P.a[j] = P.idx[j] < P.end[j] ? v : kInf;
+        }
+        const int32_t ent = gs_lds[lut_base + ((P.state << 3) | sw)];
+        const int y = ent & 1;
+        const int32_t td = t + (ent >> 1);
+        const bool chg = y != z;
+        const bool retract = t < W;
+        gs_lds[opos + (uint32_t)cnt] = td;
+        const bool app = chg && !retract;
+        cnt += app ? 1 : (chg ? -1 : 0);
+        const int32_t W0 = W;
+        W = app ? td : (chg ? Wp : W);
+        Wp = app ? W0 : Wp;
+        z = y;
+    }
+    cnt_out = cnt;
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Compacted evaluation of one staged tile group of a gate with up to three
+// pins (lane = cycle of a tile, GT tiles).  Most (gate, cycle) lanes see no
+// pin event or exactly one, and the per-tile walk runs as long as the
+// busiest lane of the tile; here the work is split by event count:
+//   1. per tile: a lane without pin events keeps its settled value and has
+//      no output edge; a lane with exactly one takes Algorithm 1's step in
+//      closed form (the pin switches at its arrival time, the truth table
+//      gives the new value, and an output edge is appended at that time plus
+//      the arc delay iff the value changes); a lane with two or more is
+//      queued with its pin ranges in the stage;
+//   2. the queued lanes of all GT tiles are walked together, 64 per pass,
+//      with interconnect filtering first when the design has wires; each
+//      writes its edges to its own region of the output stage;
+//   3. per tile: the lane counts are prefix-summed; the group reserves the
+//      exact number of output words with one atomic; lane ends, chunk
+//      headers and single edges are written, and the queued lanes copy their
+//      edges out in one more pass.
+// The SAIF terms of every lane are added to the caller's sums.  Returns
+// false, having written nothing outside the wave's LDS, when more than
+// kQueueCap lanes of the group have two or more events.
+template <int K, bool WIRES, uint32_t GT>
+__device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> &arc, uint64_t truth, uint32_t out_row,
+                                              uint32_t tile_g, uint32_t ng, int lane, uint32_t lut_base,
+                                              uint32_t out_base, uint32_t c_pos, const uint32_t (&ev)[K][GT / 2],
+                                              uint32_t salt, uint32_t &tc_sum, uint32_t &ig_sum, uint32_t &nact_sum,
+                                              int32_t &t1_lane)
+{
+    const int32_t T = win.period;
+    const uint32_t ntile = (uint32_t)win.n_tiles;
+    const uint32_t queue = out_base + kOutStageWords;
+    uint64_t mmask[GT];           // lanes queued in tile u
+    uint32_t qbase[GT];           // their first queue entry
+    int32_t e1[GT];               // a single-event lane's output edge
+    uint32_t bits = 0;            // bit u: that edge exists; bit GT + u: settled output value at t = 0
+    uint32_t qn = 0, tileoff = 0;
+
+    // 1. classify the lanes of every tile
+#pragma unroll
+    for (uint32_t u = 0; u < GT; u++) {
+        mmask[u] = 0;
+        qbase[u] = qn;
+        e1[u] = 0;
+        if (u < ng) {
+            uint32_t hi[K], lo[K], nj[K], pos[K];
+            uint32_t st0 = 0, nev = 0, lsum = 0;
+#pragma unroll
+            for (int j = 0; j < K; j++) {
+                const uint32_t w = (ev[j][u / 2] >> (16 * (u & 1))) & 0xffffu;
+                hi[j] = w & kEndCount;
+                lo[j] = wave_shr1(hi[j]);
+                nj[j] = hi[j] - lo[j];
+                st0 |= (w >> kEndInitShift) << j;
+                nev += nj[j];
+                lsum += lo[j];
+                pos[j] = (uint32_t)__builtin_amdgcn_readlane((int)c_pos, j * (int)GT + (int)u) + lo[j];
+            }
+            const uint32_t y0 = (uint32_t)(truth >> st0) & 1u;
+            // one event: the first pin with an event is the one
+            // (the wire delay by the pin's new value, selected arithmetically:
+            // a select between array elements would become an address select
+            // and force the arc arrays to scratch)
+            uint32_t p1 = pos[K - 1], sw = 1u << (K - 1);
+            int32_t dw = 0;
+            if (WIRES) {
+                const int32_t m = -(int32_t)((st0 >> (K - 1)) & 1u);
+                dw = arc.wr[K - 1] + (m & (arc.wf[K - 1] - arc.wr[K - 1]));
+            }
+#pragma unroll
+            for (int j = K - 2; j >= 0; j--) {
+                const bool h = nj[j] != 0;
+                p1 = h ? pos[j] : p1;
+                sw = h ? 1u << j : sw;
+                if (WIRES) {
+                    const int32_t m = -(int32_t)((st0 >> j) & 1u);
+                    const int32_t dj = arc.wr[j] + (m & (arc.wf[j] - arc.wr[j]));
+                    dw = h ? dj : dw;
+                }
+            }
+            const int32_t ta = gs_lds[p1] + dw;
+            const int32_t ent = gs_lds[lut_base + (((st0 ^ sw) << 3) | sw)];
+            const bool edge = nev == 1 && (uint32_t)(ent & 1) != y0;
+            e1[u] = ta + (ent >> 1);
+            bits |= (edge ? 1u << u : 0u) | (y0 << (GT + u));
+            // two or more: queue the lane
+            const bool multi = nev >= 2;
+            const uint64_t mm = __ballot(multi);
+            const uint32_t nm = (uint32_t)__popcll(mm);
+            if (qn + nm > kQueueCap) return false;
+            if (multi) {
+                const uint32_t q = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+                const uint32_t qa = queue + q * kQueueWords;
+#pragma unroll
+                for (int j = 0; j < K; j++) gs_lds[qa + j] = (int32_t)(pos[j] | ((pos[j] + nj[j]) << 16));
+                gs_lds[qa + 3] = (int32_t)((out_base + tileoff + lsum) | (st0 << 16) | (y0 << 19));
+            }
+            mmask[u] = mm;
+            qn += nm;
+#pragma unroll
+            for (int j = 0; j < K; j++) tileoff += (uint32_t)lane63(hi[j]);
+        }
+    }
+    wave_lds_sync();
+
+    // 2. walk the queued lanes, 64 at a time
+    for (uint32_t qb = 0; qb < qn; qb += kLanes) {
+        const uint32_t q = qb + (uint32_t)lane;
+        const bool valid = q < qn;
+        const uint32_t qa = queue + min(q, qn - 1) * kQueueWords;
+        Cursor<K, false, true> P;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const uint32_t w = (uint32_t)gs_lds[qa + j];
+            P.base[j] = 0;
+            P.idx[j] = w & 0xffffu;
+            P.end[j] = valid ? w >> 16 : P.idx[j];
+        }
+        const uint32_t info = (uint32_t)gs_lds[qa + 3];
+        P.state = (info >> 16) & 7u;
+        if (WIRES) {
+#pragma unroll
+            for (int j = 0; j < K; j++)
+                wire_filter_lds(0, P.idx[j], P.end[j], (P.state >> j) & 1u, arc.wr[j], arc.wf[j]);
+        }
+        int32_t cnt;
+        walk_lds_c<K>(P, (int)((info >> 19) & 1u), lut_base, info & 0xffffu, cnt);
+        if (valid) gs_lds[qa] = cnt;
+    }
+    wave_lds_sync();
+
+    // 3a. lane counts, their prefix sums and the group's exact total
+    uint32_t incl[GT];
+    uint32_t tot[GT];
+    uint32_t R = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < GT; u++) {
+        incl[u] = 0;
+        tot[u] = 0;
+        if (u < ng) {
+            const uint64_t mm = mmask[u];
+            const bool multi = (mm >> lane) & 1u;
+            uint32_t c = (bits >> u) & 1u;
+            if (multi) {
+                const uint32_t q = qbase[u] + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+                c = (uint32_t)gs_lds[queue + q * kQueueWords];
+            }
+            incl[u] = wave_incl_scan(c);
+            tot[u] = (uint32_t)lane63(incl[u]);
+            ig_sum += tot[u] - (uint32_t)__popcll(__ballot(c & 1u));
+            R += tot[u];
+        }
+    }
+    tc_sum += R;
+
+    // one reservation for the group's output chunks, exactly their words
+    const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
+    uint64_t wb = 0;
+    bool ok = true;
+    if (R > 0) {
+        if (lane == 0)
+            wb = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)R,
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wb = uniform64(wb);
+        if (wb + R > win.slice_words) {
+            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+        }
+    }
+    const uint64_t wbase = win.arena_off + (uint64_t)stripe * win.slice_words + wb;
+    int32_t *out = win.times + wbase;
+
+    // 3b. lane ends, headers, single edges; queued lanes learn their place
+    uint32_t rel = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < GT; u++) {
+        if (u < ng) {
+            const uint32_t tile = tile_g + u;
+            const int32_t first_cycle = (int32_t)(tile * kLanes);
+            const bool active = first_cycle + lane < win.n_cycles;
+            const uint32_t y0 = (bits >> (GT + u)) & 1u;
+            const uint32_t one = (bits >> u) & 1u;
+            const uint64_t ci = (uint64_t)out_row * ntile + tile;
+            const uint32_t yb = active ? y0 : 0u;
+            st_u16(win.ends + ci * kLanes, (uint32_t)lane, (uint16_t)((ok ? incl[u] : 0u) | (yb << kEndInitShift)));
+            const uint64_t mask = __ballot(yb != 0);
+            if (lane == 0) {
+                ChunkHdr h;
+                h.off = ok ? wbase + rel : 0;
+                h.mask = mask;
+                *glob(win.hdr + ci) = h;
+            }
+            const uint32_t first = rel + wave_shr1(incl[u]);
+            if (ok && one) st_word(out, first, e1[u]);
+            const uint64_t mm = mmask[u];
+            const bool multi = (mm >> lane) & 1u;
+            if (multi) {
+                const uint32_t q = qbase[u] + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+                gs_lds[queue + q * kQueueWords + 1] = (int32_t)first;
+            } else if (active) {
+                // T1 of the cycle: the settled value over [0, T), or up to
+                // the single edge and the new value after it
+                const int32_t ce = min(e1[u], T);
+                t1_lane += one ? (y0 ? ce : T - ce) : (int32_t)y0 * T;
+            }
+            const int32_t na = win.n_cycles - first_cycle;
+            nact_sum += (uint32_t)(na < 0 ? 0 : (na > kLanes ? kLanes : na));
+            rel += tot[u];
+        }
+    }
+    wave_lds_sync();
+
+    // 3c. queued lanes copy their edges out and add their T1 terms
+    for (uint32_t qb = 0; qb < qn; qb += kLanes) {
+        const uint32_t q = qb + (uint32_t)lane;
+        const bool valid = q < qn;
+        const uint32_t qa = queue + min(q, qn - 1) * kQueueWords;
+        const int32_t c = valid ? gs_lds[qa] : 0;
+        const uint32_t first = (uint32_t)gs_lds[qa + 1];
+        const uint32_t info = (uint32_t)gs_lds[qa + 3];
+        const uint32_t opos = info & 0xffffu;
+        int v = (int)((info >> 19) & 1u);
+        int32_t s1 = 0;
+        for (int32_t i = 0; i < c; i++) {
+            const int32_t e = gs_lds[opos + (uint32_t)i];
+            if (ok) st_word(out, first + (uint32_t)i, e);
+            v ^= 1;
+            const int32_t ce = min(e, T);
+            s1 += v ? -ce : ce;
+        }
+        if (valid) t1_lane += v * T + s1;
+    }
+    return true;
+}
+
 // One gate over `ntl` consecutive tiles starting at tile0 (one lane per
 // cycle of a tile).  The per-gate work (arc data, delay table) is done once.
 // Tiles are processed in groups of GT: lane c = j * GT + u fetches the
@@ -823,13 +1113,16 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         const uint32_t c_pos = stage_base + wave_shr1(c_incl);  // chunk's first word in the LDS stage
         // (the returned offset is first needed after the walk of the first tile)
         const uint32_t stripe = (blockIdx.x + sg.salt) & win.stripe_mask;
+        const bool staged = bound <= kStageWords;
+        // staged groups of gates with up to three pins take the compacted
+        // path, which reserves exactly its output words later
+        const bool try_compact = K <= 3 && staged;
         uint64_t bres = 0;
-        if (bound > 0 && lane == 0)
+        if (!try_compact && bound > 0 && lane == 0)
             bres = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)bound,
                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t wbase = 0;
         bool wok = true, placed = false;
-        const bool staged = bound <= kStageWords;
         if (!staged && lane == 0)                               // counted for the statistics
             __hip_atomic_fetch_add(glob(win.flags + 4), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // A producing wave places the chunks of its tile group one after
@@ -882,6 +1175,19 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if constexpr (K <= 3) {
+            if (try_compact) {
+                if (compact_group<K, WIRES, GT>(win, arc, g.truth, out_row, tile0 + gb, ng, lane, lut_base, out_base,
+                                                c_pos, ev, sg.salt, tc_sum, ig_sum, nact_sum, t1_lane))
+                    continue;
+                // too many lanes with two or more events: the per-tile walk
+                if (lane == 0) {
+                    __hip_atomic_fetch_add(glob(win.flags + 5), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bres = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride),
+                                                  (unsigned long long)bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
         }
         uint32_t used = 0;                                      // words of the reservation handed out
         for (uint32_t u = 0; u < ng; u++) {
@@ -1045,8 +1351,10 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int n, uin
 }
 
 // Wave w of a launch -> (segment, gate, group of tpw consecutive tiles).
-// LDS per wave: 64 words of delay table, (CAP + 1) x 64 staged output words
-// (the last slot of each lane is a spare), then the staged fanin words.
+// LDS per wave: 64 words of delay table, the staged fanin words, then either
+// (CAP + 1) x 64 staged output words of the per-tile path (the last slot of
+// each lane is a spare) or the output stage and lane queue of the compacted
+// path.
 template <bool WIRES, int CAP, int KMAX, bool REMAP>
 __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ segs, int32_t n_segs, uint64_t n_waves,
                                                         uint32_t tpw)
@@ -1072,9 +1380,9 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const uint32_t tile0 = grp * tpw;
     const uint32_t ntl = min(tpw, ntile - tile0);
     const GateRec g = *kons(sg.gates + sg.gate_begin + gi);
-    const uint32_t lut_base = wib * (kLanes + (CAP + 1) * kLanes + kStageWords);
-    const uint32_t out_base = lut_base + kLanes;
-    const uint32_t stage_base = out_base + (CAP + 1) * kLanes;
+    const uint32_t lut_base = wib * (uint32_t)gate_eval_wave_words(CAP);
+    const uint32_t stage_base = lut_base + kLanes;
+    const uint32_t out_base = stage_base + kStageWords;
     switch (g.k) {
     case 1: eval_gate<1, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
     case 2: eval_gate<2, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;

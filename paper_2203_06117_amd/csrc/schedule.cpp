@@ -279,6 +279,7 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     ctx->stats.arena_words = (int64_t)used;
     ctx->stats.spilled_lanes += f32[2];
     ctx->stats.unstaged_groups += f32[4];
+    ctx->stats.queue_overflows += f32[5];
     if (f32[3]) return gs_fail(ctx, GS_E_DEVICE, "internal error: an output chunk exceeded its fanin bound");
     if (f32[1]) return gs_fail(ctx, GS_E_CAPACITY, "more than %u transitions in one (net, 64-cycle tile)", kMaxChunk);
     if (f32[0]) {

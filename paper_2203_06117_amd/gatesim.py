@@ -56,7 +56,8 @@ class Stats(C.Structure):
     _fields_ = [("gate_eval_ms", C.c_double), ("expand_ms", C.c_double), ("wall_ms", C.c_double),
                 ("gate_eval_launches", C.c_int64), ("windows", C.c_int64), ("window_retries", C.c_int64),
                 ("gate_cycles", C.c_int64), ("spilled_lanes", C.c_int64), ("arena_words", C.c_int64),
-                ("graph_launches", C.c_int64), ("unstaged_groups", C.c_int64), ("reserved", C.c_int64 * 4)]
+                ("graph_launches", C.c_int64), ("unstaged_groups", C.c_int64), ("queue_overflows", C.c_int64),
+                ("reserved", C.c_int64 * 3)]
 
 
 class Tuning(C.Structure):
