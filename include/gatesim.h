@@ -227,6 +227,25 @@ gs_status gs_segment_stimulus(gs_ctx *ctx, int32_t stim, int32_t segment_cycles,
  * GS_E_DEVICE. */
 gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * re-simulation and SAIF accumulation as gs_simulate, with the same result,
+ * but every device buffer the call needs beyond the loaded design and
+ * stimulus (window chunk headers, lane ends and transition arena, flags,
+ * stripe counters, the level segment table) lives in a static device array
+ * of GS_SCRATCH_BYTES per GPU, which the library holds from gs_create until
+ * the process ends.  The call makes no device allocation and no graph
+ * capture; it runs direct launches on the context's stream, synchronously.
+ * Windows are as long as their chunk headers and lane ends fit in half of the
+ * scratch, and are halved when the transition arena fills up.  Calls on one
+ * GPU share its scratch, which keeps the last call's contents: calls that
+ * overlap on one GPU (other threads or contexts) race.  gs_read_waveform
+ * does not see windows run by this call.  Errors: as gs_simulate, and
+ * GS_E_NOMEM when a 64-cycle window of the design (144 bytes per net) or its
+ * levels (at most 6,241) do not fit the scratch. */
+#define GS_SCRATCH_BYTES (64ull << 20)
+gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end);
+
 /* Copies the design's accumulated SAIF counts, n_inputs + n_gates entries
  * each, into caller arrays (any may be NULL); nonzero reset zeroes the
  * accumulators afterwards.  Page-locked arrays (hipHostMalloc) are filled

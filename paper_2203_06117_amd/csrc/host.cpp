@@ -214,6 +214,9 @@ static gs_status dev_alloc(gs_ctx *ctx, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) return GS_OK;
+    if (ctx && ctx->noalloc)
+        return gs_fail(ctx, GS_E_NOMEM, "the allocation-free call needs %zu more bytes than its static scratch "
+                       "holds", bytes);
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -299,6 +302,15 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
         return gs_fail(nullptr, GS_E_NOMEM, "small allocation failed");
     }
     ctx->d_bump = (unsigned long long *)p;
+    // this device's static scratch (allocation-free simulate), looked up now
+    // while the device is current
+    hipError_t se = scratch_region(o.device, &p);
+    if (se != hipSuccess) {
+        (void)hipGetLastError();
+        gs_destroy(ctx);
+        return gs_fail(nullptr, GS_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(se));
+    }
+    ctx->d_scratch = (char *)p;
     *out = ctx;
     return GS_OK;
 }
@@ -657,8 +669,11 @@ gs_status gs_window_reserve(gs_ctx *ctx, WindowBufs *w, uint64_t n_chunks, uint6
         // carve [hdr | ends | times] out of the caller's arena
         uint64_t hb = (n_chunks * sizeof(ChunkHdr) + 255) & ~255ull;
         uint64_t eb = (n_chunks * kLanes * sizeof(uint16_t) + 255) & ~255ull;
-        uint64_t tb = words * sizeof(int32_t);
-        if (hb + eb + tb > ctx->opt.arena_bytes) return gs_fail(ctx, GS_E_NOMEM, "arena too small for the window");
+        // the window gets all the space left after its headers and lane ends
+        // (the planner's byte count leaves out the 256-byte alignment above)
+        (void)words;
+        if (hb + eb + (64ull << 10) > ctx->opt.arena_bytes)
+            return gs_fail(ctx, GS_E_NOMEM, "arena too small for the window");
         char *base = (char *)ctx->opt.arena;
         w->hdr = (ChunkHdr *)base;
         w->ends = (uint16_t *)(base + hb);

@@ -138,6 +138,10 @@ struct gs_ctx {
     unsigned long long *d_late = nullptr;    // late nets
     const int32_t *d_wout = nullptr;         // per net: slowest fanout wire, rise and fall (null: no wires)
     int32_t profile_begin = 0;               // the cycle of entry 0
+    // this GPU's static scratch (gs_simulate_noalloc); while noalloc is set,
+    // every device allocation the library would make fails instead
+    char *d_scratch = nullptr;
+    bool noalloc = false;
     std::map<std::string, std::array<int32_t, 3>> tuned;   // autotuned (cap, wpb, tpw) per batch shape
     // serving
     ServeState *serve = nullptr;

@@ -151,6 +151,16 @@ struct StimView {
     int32_t period;
 };
 
+// Static device scratch of gs_simulate_noalloc (bytes per GPU), and the
+// devices whose scratch address is kept.
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr int kMaxDevices = 64;
+
+// Address of this GPU's static scratch: looked up with hipGetSymbolAddress
+// on the first call for a device, which must be the current device then,
+// and kept for later calls.
+hipError_t scratch_region(int device, void **ptr);
+
 // ---- launchers (kernels.hip) ------------------------------------------
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int *p, uint64_t n, unsigned int v, hipStream_t s);

@@ -7,7 +7,38 @@
 // the 64 lanes of a wave read neighbouring words of the same chunk.
 #include "internal.h"
 
+#include <mutex>
+
 namespace gs {
+
+// --------------------------------------------------------------------------
+// Static device scratch of the allocation-free simulate call: one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it names a stand-in, not device memory); it uses
+// the per-device address that scratch_region looks up once per device.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_region(int device, void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current first
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 // Explicit global address space: pointers read out of the segment table
 // would otherwise stay generic and every access would become a flat

@@ -11,6 +11,9 @@
 
 using namespace gs;
 
+static_assert(kScratchBytes == GS_SCRATCH_BYTES, "the public scratch size and the device array differ");
+static_assert(sizeof(Seg) == 168, "segment table capacity of the static scratch is documented for 168-byte segments");
+
 #define HIPCHK(x)                                                                                  \
     do {                                                                                           \
         hipError_t e_ = (x);                                                                       \
@@ -178,6 +181,7 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     // per-piece first cycle lives in device memory so that a captured graph
     // can be replayed for another window of the same shape
     if (ctx->c0_cap < pieces.size()) {
+        if (ctx->noalloc) return gs_fail(ctx, GS_E_NOMEM, "round parameter block outgrows the static scratch");
         gs_dev_free(ctx->d_c0);
         ctx->d_c0 = nullptr;
         ctx->c0_cap = 0;
@@ -527,6 +531,87 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
     }
     ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
     return GS_OK;
+}
+
+// The allocation-free variant of gs_simulate.  Every buffer a round needs
+// beyond the loaded design and stimulus comes from this GPU's static scratch,
+// in this order: flags and counters, stripe counters, the first-cycle block,
+// the segment table, then the window (chunk headers, lane ends, transition
+// arena, carved as for a caller-owned arena).  Windows are as long as the
+// headers fit in half of the window region; a full arena halves them.  The
+// context's own buffers, options and learned window length are restored on
+// return.  Calls that overlap on one GPU share the scratch and race.
+extern "C" gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin,
+                                         int32_t cycle_end)
+{
+    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
+    if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
+    gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
+    if (st) return st;
+    if (!ctx->d_scratch) return gs_fail(ctx, GS_E_STATE, "no static scratch on this device");
+    (void)hipSetDevice(ctx->opt.device);
+    Design *d = ctx->designs[design];
+    constexpr size_t kMiscBytes = 256, kBumpBytes = sizeof(unsigned long long) * kMaxStripes * kBumpStride;
+    constexpr size_t kC0Slots = 64, kSegBytes = 1u << 20;
+    char *base = ctx->d_scratch;
+    char *misc = base, *bump = misc + kMiscBytes, *c0 = bump + kBumpBytes, *segs = c0 + 256;
+    char *win = segs + kSegBytes;
+    const size_t win_bytes = kScratchBytes - (size_t)(win - base);
+    const size_t seg_cap = kSegBytes / sizeof(Seg);
+    if ((size_t)d->L > seg_cap)
+        return gs_fail(ctx, GS_E_NOMEM, "%d levels exceed the %zu segments of the static scratch", d->L, seg_cap);
+    if (gs_header_bytes((uint64_t)d->N, kLanes) * 2 > win_bytes)
+        return gs_fail(ctx, GS_E_NOMEM, "a 64-cycle window of %d nets needs %llu bytes of chunk headers and lane "
+                       "ends; the static scratch holds %zu bytes for windows", d->N,
+                       (unsigned long long)gs_header_bytes((uint64_t)d->N, kLanes), win_bytes);
+    int32_t W = 16384;
+    while (W > kLanes && gs_header_bytes((uint64_t)d->N, W) * 2 > win_bytes) W /= 2;
+
+    struct Saved {
+        gs_options opt;
+        uint64_t budget;
+        WindowBufs win;
+        unsigned long long *misc, *bump;
+        Seg *segs;
+        size_t segs_cap;
+        int32_t *c0;
+        size_t c0_cap;
+        int32_t window_fit;
+    } sv{ctx->opt, ctx->budget, ctx->win, ctx->d_misc, ctx->d_bump, ctx->d_segs, ctx->segs_cap, ctx->d_c0,
+         ctx->c0_cap, d->window_fit};
+    ctx->opt.arena = win;
+    ctx->opt.arena_bytes = win_bytes;
+    ctx->opt.schedule = GS_SCHED_LEVELS;
+    ctx->budget = win_bytes;
+    ctx->win = WindowBufs();
+    ctx->d_misc = (unsigned long long *)misc;
+    ctx->d_bump = (unsigned long long *)bump;
+    ctx->d_segs = (Seg *)segs;
+    ctx->segs_cap = seg_cap;
+    ctx->d_c0 = (int32_t *)c0;
+    ctx->c0_cap = kC0Slots;
+    ctx->noalloc = true;
+    const uint64_t t_start = gs_now_ns();
+    for (int32_t b = cycle_begin; b < cycle_end && st == GS_OK; b += W) {
+        const Piece p = make_piece(ctx, design, stim, b, std::min(W, cycle_end - b));
+        st = run_pieces(ctx, std::vector<Piece>{p}, tuning_for(ctx, {p}), true, false, nullptr);
+    }
+    if (st == GS_OK && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        st = gs_fail(ctx, GS_E_DEVICE, "stream synchronisation failed");
+    ctx->noalloc = false;
+    ctx->opt = sv.opt;
+    ctx->budget = sv.budget;
+    ctx->win = sv.win;
+    ctx->d_misc = sv.misc;
+    ctx->d_bump = sv.bump;
+    ctx->d_segs = sv.segs;
+    ctx->segs_cap = sv.segs_cap;
+    ctx->d_c0 = sv.c0;
+    ctx->c0_cap = sv.c0_cap;
+    d->window_fit = sv.window_fit;
+    ctx->last = LastWindow();                  // the scratch window is not kept for gs_read_waveform
+    ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
+    return st;
 }
 
 // Times each candidate tuning on a trial window (nothing committed) and

@@ -102,6 +102,7 @@ _SIGS = {
     "gs_glitch_profile": (I32, [P, I32, I32, I32, I32, P]),
     "gs_cycle_profile": (I32, [P, I32, I32, I32, I32, P, P]),
     "gs_simulate": (I32, [P, I32, I32, I32, I32]),
+    "gs_simulate_noalloc": (I32, [P, I32, I32, I32, I32]),
     "gs_read_saif": (I32, [P, I32, P, P, P, I32]),
     "gs_read_saif_ig": (I32, [P, I32, P, P, P, P, I32]),
     "gs_read_waveform": (I32, [P, I32, I32, I32, I32, C.POINTER(I32), P, I32, C.POINTER(I32)]),
@@ -303,6 +304,10 @@ class GateSim:
     # -- running ---------------------------------------------------------
     def simulate(self, design, stim, cycle_begin, cycle_end):
         self._chk(_lib.gs_simulate(self._h, design, stim, int(cycle_begin), int(cycle_end)))
+
+    def simulate_noalloc(self, design, stim, cycle_begin, cycle_end):
+        """gs_simulate_noalloc: the same result through the static device scratch."""
+        self._chk(_lib.gs_simulate_noalloc(self._h, design, stim, int(cycle_begin), int(cycle_end)))
 
     def read_saif(self, design, reset=False, out=None):
         """TC, T0, T1 per net.  ``out``: three caller-owned int64 arrays of
