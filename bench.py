@@ -7,9 +7,11 @@ tables and input waveforms already resident in device memory.  The value is
 gates x cycles per second over the timed steps.
 
 Also reported (one JSON line):
-  roofline      algorithmic bytes of the gate-evaluation kernel / its average
-                launch time (HIP events on the library's stream) vs 8 TB/s,
-                with the measured HBM traffic and a copy kernel's bandwidth
+  roofline      compulsory bytes of the gate-evaluation kernel's work (B_min per
+                gate-cycle) / its average launch time (HIP events on the
+                library's stream) vs 8 TB/s, with the measured HBM traffic,
+                a per-sink byte model and a copy kernel's bandwidth
+  windows_1000  the same workload in 1,000-cycle windows
   cpu_baseline  the CPU oracle timed on bounded samples of the same workload:
                 one process per host core, and single-threaded (whose SAIF
                 also re-checks the GPU result)
@@ -41,13 +43,26 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "gate-cycles/s + % HBM roofline (1M gates); batched req/s, p50/p99 latency"
 
 
-def algorithmic_bytes(net, tc, n_cycles, n_tiles):
-    """Bytes the gate-evaluation kernel must move for the simulated cycles:
-    per gate, every fanin list is read once per sink and the output list is
-    written once (4 B per transition, 2 B lane end + 16 B chunk header per
-    64-cycle tile per list), plus the gate's 32 B record, 48 B per pin
-    (net, condition pin, 8-entry delay row, wire delays) and 24 B of SAIF
-    atomics per tile."""
+# Compulsory bytes per gate-cycle (the roofline's algorithmic bytes):
+# B_min = 2 (h + 4 a) + eps.  Every (net, cycle) list is written once and
+# read once: h = 2 B lane end + a 16 B chunk header per 64 cycles, 4 B per
+# transition (a = transitions per gate and cycle, measured), and eps = 1 B
+# of gate record and SAIF atomics per gate-cycle, amortized over a tile.
+H_BYTES = 2.0 + 16.0 / 64
+EPS_BYTES = 1.0
+
+
+def compulsory_bytes_per_gate_cycle(a_bar):
+    return 2.0 * (H_BYTES + 4.0 * a_bar) + EPS_BYTES
+
+
+def per_sink_bytes(net, tc, n_cycles, n_tiles):
+    """A second byte model of the gate-evaluation kernel, with no cache
+    reuse across a net's fanouts: per gate, every fanin list is read once
+    per sink and the output list is written once (4 B per transition, 2 B
+    lane end + 16 B chunk header per 64-cycle tile per list), plus the
+    gate's 32 B record, 48 B per pin (net, condition pin, 8-entry delay
+    row, wire delays) and 24 B of SAIF atomics per tile."""
     I, Gn = net["n_inputs"], net["n_gates"]
     fp, fn = net["fanin_ptr"], net["fanin_net"]
     k = np.diff(fp)
@@ -157,27 +172,13 @@ def run_scale(args, torch, synth, GateSim):
     g_tc, _, _, g_ig = sim.read_saif_ig(d, reset=True)
     glitch_share = float(g_ig[net["n_inputs"]:].sum()) / max(1.0, float(g_tc[net["n_inputs"]:].sum()))
     n_tiles_total = sum((min(window, C - c0) + 63) // 64 for c0 in range(0, C, window))
-    alg_bytes_step = algorithmic_bytes(net, tc, C, n_tiles_total)
+    sink_bytes_step = per_sink_bytes(net, tc, C, n_tiles_total)
+    a_bar = float(tc[net["n_inputs"]:].sum()) / (Gn * C)
+    b_min = compulsory_bytes_per_gate_cycle(a_bar)
     launches = st["gate_eval_launches"]
     roofline = None
     if not args.no_timing and launches:
-        avg_launch_s = st["gate_eval_ms"] / 1e3 / launches
-        per_launch_bytes = alg_bytes_step * args.steps / launches
-        achieved = per_launch_bytes / avg_launch_s / 1e9
-        rec = measured_counters()
-        traffic = rec["traffic_bytes_per_launch"] if rec else None
-        # VALU issue: a wave64 instruction occupies a 16-lane SIMD for 4
-        # cycles; 1,024 SIMDs at the nominal 2.4 GHz
-        valu = rec.get("valu_insts_per_launch") if rec else None
-        valu_frac = round(valu * 4 / 1024 / (avg_launch_s * 2.4e9), 4) if valu else None
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "traffic_gbs": round(traffic / avg_launch_s / 1e9, 1) if traffic else None,
-                    "copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
-                    "kernel": "gate_eval_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                    "launches": launches, "bytes_per_launch": round(per_launch_bytes),
-                    "bytes_per_gate_cycle": round(alg_bytes_step / (Gn * C), 3),
-                    "valu_insts_per_launch": valu, "valu_issue_frac": valu_frac}
+        roofline = roofline_of(st, Gn * C * args.steps, b_min, sink_bytes_step * args.steps, a_bar, copy_gbs)
     cpu = None
     if args.cpu_cycles > 0:
         import oracle
@@ -211,7 +212,7 @@ def run_scale(args, torch, synth, GateSim):
                "single_core": single, "host_cpu": host_cpu(), "nproc": os.cpu_count(),
                "gpu_parity_on_sample": parity}
     sim.close()
-    a_bar = float(tc[net["n_inputs"]:].sum()) / (Gn * C)
+    windowed = run_scale_windows(args, torch, w, GateSim, b_min) if args.window_leg else None
     return {
         "value": round(gate_cycles / elapsed, 1),
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
@@ -226,7 +227,75 @@ def run_scale(args, torch, synth, GateSim):
         "window_retries": st["window_retries"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "windows_1000": windowed,
     }
+
+
+def roofline_of(st, gate_cycles, b_min, sink_bytes, a_bar, copy_gbs):
+    """The gate-evaluation kernel against the HBM roofline.  `achieved` and
+    `frac` count the compulsory bytes (B_min per gate-cycle) of the work
+    one launch does, over the average launch time from HIP events on the
+    library's stream.  Beside them: the measured DRAM traffic per launch
+    (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, from the committed
+    counter summary while the kernel source is unchanged), its ratio to
+    B_min, and the per-sink byte model."""
+    launches = st["gate_eval_launches"]
+    avg_launch_s = st["gate_eval_ms"] / 1e3 / launches
+    gc_launch = gate_cycles / launches
+    achieved = b_min * gc_launch / avg_launch_s / 1e9
+    rec = measured_counters()
+    traffic = rec["traffic_bytes_per_launch"] if rec else None
+    # VALU issue: a wave64 instruction occupies a 16-lane SIMD for 4
+    # cycles; 1,024 SIMDs at the nominal 2.4 GHz
+    valu = rec.get("valu_insts_per_launch") if rec else None
+    valu_frac = round(valu * 4 / 1024 / (avg_launch_s * 2.4e9), 4) if valu else None
+    sink_gbs = sink_bytes / launches / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "gate_eval_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": launches,
+            "gate_cycles_per_launch": round(gc_launch),
+            "b_min_bytes_per_gate_cycle": round(b_min, 3),
+            "b_min_terms": {"h_bytes": H_BYTES, "a_bar": round(a_bar, 4), "eps_bytes": EPS_BYTES},
+            "bytes_per_launch": round(b_min * gc_launch),
+            "traffic_gbs": round(traffic / avg_launch_s / 1e9, 1) if traffic else None,
+            "traffic_frac": round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+            "traffic_over_bmin": round(traffic / (b_min * gc_launch), 3) if traffic else None,
+            "per_sink_model": {"bytes_per_gate_cycle": round(sink_bytes / gate_cycles, 3),
+                               "gbs": round(sink_gbs, 1), "frac": round(sink_gbs / HBM_PEAK_GBS, 4)},
+            "copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+            "valu_insts_per_launch": valu, "valu_issue_frac": valu_frac}
+
+
+def run_scale_windows(args, torch, w, GateSim, b_min):
+    """The same workload in the 1,000-cycle windows the configuration names
+    (ten windows per step instead of one), beside the headline."""
+    net, stim = w["netlist"], w["stimulus"]
+    Gn, C = net["n_gates"], stim["n_cycles"]
+    sim = GateSim(device=0, stream=torch.cuda.current_stream(), window_cycles=1000, lds_cap=args.lds_cap,
+                  waves_per_block=args.wpb, timing=True, tiles_per_wave=args.tpw)
+    d, s = sim.load_work(w)
+    sim.simulate(d, s, 0, C)
+    sim.read_saif(d, reset=True)
+    steps = max(1, min(args.steps, 3))
+    sim.stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.simulate(d, s, 0, C)
+        sim.read_saif(d, reset=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    launches = st["gate_eval_launches"]
+    avg_s = st["gate_eval_ms"] / 1e3 / launches
+    gc_launch = Gn * C * steps / launches
+    log(f"1000-cycle windows: {steps} steps in {elapsed:.3f}s, {avg_s * 1e6:.1f} us per gate-eval launch")
+    return {"window_cycles": 1000, "steps": steps, "value": round(Gn * C * steps / elapsed, 1),
+            "unit": "gate-cycles/s", "ms_per_step": round(elapsed / steps * 1e3, 3),
+            "kernel_gate_cycles_per_s": round(Gn * C * steps / (st["gate_eval_ms"] / 1e3), 1),
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+            "frac": round(b_min * gc_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def run_batch(args, torch, synth, G):
@@ -424,7 +493,7 @@ def run_serve(args, torch, synth, G):
     sample = set(int(x) for x in rng.choice(len(plan), size=min(40, len(plan)), replace=False))
     tickets = [None] * len(plan)
     kept = {}
-    lat, gcs, done_t, sub_t, status = [], [], [], [], []
+    lat, gcs, done_t, sub_t, adm_t, status = [], [], [], [], [], []
     lock = threading.Lock()
 
     def submit(p):
@@ -456,8 +525,9 @@ def run_serve(args, torch, synth, G):
             gcs.append(r["gate_cycles"])
             done_t.append(r["t_done_ns"])
             sub_t.append(r["t_submit_ns"])
+            adm_t.append(r["t_admit_ns"])
             if j in sample and r["status"] == 0:
-                kept[j] = (r["tc"], r["t0"], r["t1"])
+                kept[j] = (r["tc"], r["t0"], r["t1"], r["ig"])
             if (j + 1) % 2000 == 0:
                 log(f"served {j + 1}/{len(plan)} requests")
 
@@ -473,18 +543,32 @@ def run_serve(args, torch, synth, G):
         tk = submit(plan[j])
         r = sim.poll(tk, wait=True)
         sim.release(tk)
-        same &= r["status"] == 0 and all(np.array_equal(a, b) for a, b in zip((r["tc"], r["t0"], r["t1"]), kept[j]))
+        same &= r["status"] == 0 and all(np.array_equal(a, b)
+                                         for a, b in zip((r["tc"], r["t0"], r["t1"], r["ig"]), kept[j]))
     sim.serve_stop()
     sim.close()
     lat = np.array(lat)
     ok = int(sum(1 for x in status if x == 0))
+    # requests on the device together: admitted and not yet finished
+    ev = sorted([(a, 1) for a in adm_t] + [(d, -1) for d in done_t])
+    cur = peak = 0
+    busy = area = 0.0
+    last = ev[0][0] if ev else 0
+    for t, dlt in ev:
+        if cur > 0:
+            busy += t - last
+            area += cur * (t - last)
+        cur += dlt
+        peak = max(peak, cur)
+        last = t
     log(f"served {ok}/{len(plan)} ok, {ok / wall:.1f} req/s, p50 {np.percentile(lat, 50):.1f} ms, "
         f"p99 {np.percentile(lat, 99):.1f} ms, alone==mix on {len(kept)} sampled: {same}")
     return {"workload": "served-9", "offered_req_per_s": rate, "seconds": dur, "requests": len(plan),
             "completed_ok": ok, "value": round(ok / wall, 2), "unit": "req/s",
             "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "served_gate_cycles_per_s": round(float(sum(gcs)) / wall, 1),
-            "alone_equals_mix_sampled": bool(same), "sampled": len(kept)}
+            "alone_equals_mix_sampled": bool(same), "sampled": len(kept),
+            "max_in_flight": peak, "mean_in_flight_while_busy": round(area / busy, 2) if busy else 0.0}
 
 
 def main():
@@ -500,6 +584,8 @@ def main():
     ap.add_argument("--wpb", type=int, default=4)
     ap.add_argument("--cpu-cycles", type=int, default=30, help="oracle sample: first N cycles (0 = skip)")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--no-window-leg", dest="window_leg", action="store_false",
+                    help="skip the 1,000-cycle-window figure of the scale leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one elementwise kernel over this many MiB first (counter calibration)")
     ap.add_argument("--serve-rate", type=float, default=200.0)

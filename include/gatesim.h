@@ -85,7 +85,9 @@ typedef struct {
     void    *arena;           /* optional caller-owned device buffer used for all waveform storage */
     uint64_t arena_bytes;
     int32_t  window_cycles;   /* cycles per window; 0 = as many as fit the budget, capped at 16384 */
-    int32_t  lds_cap;         /* transitions per (net, cycle) staged on chip before the spill path: 4, 8, 16 or 32;
+    int32_t  lds_cap;         /* transitions per (net, cycle) staged on chip by the per-tile walk (tile groups
+                                 too large for the on-chip stage, cells of four or more pins, overflowing
+                                 queues) before its spill path: 4, 8, 16 or 32;
                                  0 = chosen per round from the input toggles per (input, cycle), or the
                                  transitions per (net, cycle) the design showed in its last round if higher:
                                  8 up to 0.5, 16 up to 1, else 32 (segment views carry many cycles per lane,
@@ -103,13 +105,21 @@ typedef struct {
 /* Fills *opt with the defaults above. */
 void gs_default_options(gs_options *opt);
 
-/* Creates a context on opt->device (opt may be NULL for defaults).
- * Errors: GS_E_DEVICE if the device cannot be used, GS_E_INVALID. */
+/* Creates a context on opt->device (opt may be NULL for defaults): the
+ * device memory the netlists, delay tables and waveforms live in, and the
+ * stream the work runs on (the paper keeps the design and one preallocated
+ * waveform chunk resident in GPU memory, Section 3).  Errors: GS_E_DEVICE
+ * if the device cannot be used, GS_E_INVALID. */
 gs_status gs_create(const gs_options *opt, gs_ctx **out);
+
+/* Frees every device buffer of the context (not a caller-owned arena) and
+ * its streams; a serving loop still running is stopped first.  NULL is a
+ * no-op.  (Resource management of this library; no passage of the paper.) */
 gs_status gs_destroy(gs_ctx *ctx);
 
 /* Message for the last failure of ctx, or of a context-free call on this
- * thread when ctx is NULL.  Valid until the next call on the same ctx. */
+ * thread when ctx is NULL.  Valid until the next call on the same ctx.
+ * (Error reporting of this library; no passage of the paper.) */
 const char *gs_last_error(gs_ctx *ctx);
 
 /* Cell library (Algorithm 1's truth table Y[2^n]): cell c has n_pins[c]
@@ -261,9 +271,12 @@ gs_status gs_read_saif_ig(gs_ctx *ctx, int32_t design, int64_t *tc, int64_t *t0,
                           int32_t reset);
 
 /* Debug/spot-check read of one net's waveform in one cycle of the most
- * recently simulated window of (design, stim): *init gets the value at
- * t = 0, *n the number of edges, times[0 .. min(*n, cap)) the edge times in
- * cycle-local ps.  GS_E_STATE if the cycle is not resident. */
+ * recently simulated window of (design, stim): the output list Algorithm 1
+ * writes for a (net, cycle), as its initial value and edge times.  *init
+ * gets the value at t = 0, *n the number of edges, times[0 .. min(*n, cap))
+ * the edge times in cycle-local ps.  GS_E_STATE if the cycle is not
+ * resident (windows of gs_simulate_noalloc and of the batch and serving
+ * calls are not kept). */
 gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim, int32_t net, int32_t cycle,
                            int32_t *init, int32_t *times, int32_t cap, int32_t *n);
 
@@ -325,12 +338,20 @@ typedef struct {
     int32_t cycle_end;
 } gs_job;
 
+/* Runs the jobs as rounds that fit the memory budget; level k of every job
+ * of a round is one launch, and a round's launches are replayed from a
+ * captured HIP graph when the schedule is GS_SCHED_GRAPH.  The paper runs
+ * one design per invocation and pays a stream synchronisation and kernel
+ * launch per level (Section 5, Table 5); batching shares those costs among
+ * the jobs.  Errors: as gs_simulate for each job (checked before any work). */
 gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job *jobs);
 
 /* Autotuner: times candidate (lds_cap, waves_per_block, tiles_per_wave)
  * settings of the gate-evaluation kernel on cycles [cycle_begin, cycle_end)
  * (at most 4096) of (design, stim), with nothing added to the SAIF
- * accumulators, and keeps the fastest in the context's options. */
+ * accumulators, and keeps the fastest in the context's options.  The paper
+ * tunes its cycle parallelism and threads per block by measurement
+ * (Section 5, Table 6); these are the corresponding knobs here. */
 typedef struct {
     int32_t lds_cap, waves_per_block, tiles_per_wave, reserved;
     double  trial_ms;           /* gate-evaluation time of the winning setting on the trial */

@@ -113,7 +113,9 @@ def test_edit_requests(served):
 
 def test_alone_equals_mix(served):
     """Each request's result is the same when it runs alone and when it runs
-    concurrently with others submitted from several threads."""
+    concurrently with others submitted from several threads; in the mixed
+    phase requests are on the device together (a request is admitted before
+    another one has finished)."""
     sim, works, ids, _ = served
     rng = np.random.default_rng(3)
     plan = []
@@ -144,9 +146,17 @@ def test_alone_equals_mix(served):
         t.start()
     for t in ths:
         t.join()
+    spans = []
     for j, t in enumerate(tickets):
         r = result_of(sim, t)
         same((r["tc"], r["t0"], r["t1"], r["ig"]), alone[j], f"request {j}")
+        spans.append((r["t_admit_ns"], r["t_done_ns"]))
+    # pairs of requests whose [admit, done] intervals overlap: both were
+    # admitted and neither had finished
+    overlap = sum(1 for a in range(len(spans)) for b in range(a + 1, len(spans))
+                  if spans[a][0] < spans[b][1] and spans[b][0] < spans[a][1])
+    say("alone == mix: overlapping request pairs", overlap)
+    assert overlap >= 4, spans
 
 
 def test_bad_edit_is_rejected(served):
