@@ -50,7 +50,7 @@ def _load():
     lib.oracle_level.restype = C.c_int32
     lib.oracle_run.restype = C.c_int32
     lib.oracle_run.argtypes = [P, C.c_int32, C.c_int32, P, P, P, C.c_int32, C.c_int32,
-                               P, P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_int32, P]
+                               P, P, P, P, P, P, C.c_int32, P, P, P, P, P, C.c_int32, P, C.c_int32]
     _lib = lib
     return lib
 
@@ -112,7 +112,7 @@ class Oracle:
         return _load().oracle_level(self._h, int(net))
 
     def run(self, stim: dict, cycle_begin: int = 0, cycle_end: int | None = None,
-            probes=None, probe_cap: int = 4096, segment_cycles: int = 1):
+            probes=None, probe_cap: int = 4096, segment_cycles: int = 1, net_filter: bool = True):
         """Simulate cycles [cycle_begin, cycle_end).
 
         Returns a dict with int64 arrays tc, t0, t1 and ig (glitch toggles; one
@@ -131,6 +131,10 @@ class Oracle:
         interval: cycle_begin / cycle_end and probe cycles count groups,
         probe times are local to the group, T0 / T1 cover the group, and ig
         counts each group's edges beyond its net value change.
+
+        net_filter False: transport wire delays, Algorithm 1 without its
+        net-delay filtering lines (the feature study of Section 5, Table 7);
+        see oracle.c.
         """
         lib = _load()
         S = int(segment_cycles)
@@ -161,7 +165,8 @@ class Oracle:
         stats = np.zeros(2, dtype=np.int64)
         rc = lib.oracle_run(self._h, int(stim["period"]), int(stim["n_cycles"]), _p(init), _p(tp), _p(ts),
                             int(cycle_begin), int(cycle_end), _p(tc), _p(t0), _p(t1), _p(ig), _p(ig_cycle), _p(late_cycle),
-                            npb, _p(pn), _p(pc), _p(pi), _p(pl), _p(pt), probe_cap, _p(stats))
+                            npb, _p(pn), _p(pc), _p(pi), _p(pl), _p(pt), probe_cap, _p(stats),
+                            1 if net_filter else 0)
         if rc != 0:
             raise OracleError("oracle internal inconsistency")
         out = []
@@ -176,6 +181,8 @@ class Oracle:
 
 def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, probes=None,
              segment_cycles: int = 1):
-    """Convenience: load ``work`` (a synth workload dict) and run it."""
+    """Convenience: load ``work`` (a synth workload dict) and run it.  A
+    ``net_filter`` key set to False selects transport wire delays."""
     o = Oracle(work["netlist"], work["arcs"], work.get("wires"))
-    return o.run(work["stimulus"], cycle_begin, cycle_end, probes, segment_cycles=segment_cycles)
+    return o.run(work["stimulus"], cycle_begin, cycle_end, probes, segment_cycles=segment_cycles,
+                 net_filter=work.get("net_filter", True))

@@ -12,7 +12,11 @@ Algorithm 1 walks one gate's input waveforms:
    list with the interconnect inertial rule of Algorithm 1: walking the
    net's changes in order, a change at e_k followed by one at e_(k+1) with
    e_(k+1) - e_k < delta(e_k) drops both; otherwise the pin changes at
-   e_k + delta(e_k), delta chosen by the value the net changes to.
+   e_k + delta(e_k), delta chosen by the value the net changes to.  With
+   ``net_filter`` False in the work dict (the feature study's wire delays
+   without that filter) every change arrives at e_k + delta(e_k), kept on a
+   stack: an arrival no later than the stack's top cancels it and is itself
+   dropped (a pulse of non-positive delayed width).
 3. The gate's zero-delay response y(t) = truth[pins(t)] is sampled at every
    picosecond.  At each t where y changes, the pins that switched at t give
    the arc delay: the smallest over those pins of the arc's delay for the new
@@ -82,9 +86,21 @@ def _samples(v0, change_times, H):
     return out
 
 
-def _wire(net_samples, dr, df, H):
+def _wire(net_samples, dr, df, H, net_filter=True):
     v0 = net_samples[0]
     e = _changes(net_samples)
+    if not net_filter:
+        # transport delay: every change arrives at e + delta; a pulse whose
+        # delayed end is no later than its delayed start vanishes, which may
+        # expose an older arrival to the next change
+        out = []
+        for t in e:
+            a = t + (dr if net_samples[t + 1] else df)
+            if out and out[-1] >= a:
+                out.pop()
+            else:
+                out.append(a)
+        return _samples(v0, out, H)
     out = []
     k = 0
     while k < len(e):
@@ -150,7 +166,7 @@ def simulate(work: dict, cycle_begin: int = 0, cycle_end: int | None = None, hor
             S[i] = _samples(v0, loc, H)
         for g in order:
             k = fp[g + 1] - fp[g]
-            pins = [_wire(S[fn[s]], wr[s], wf[s], H) for s in range(fp[g], fp[g + 1])]
+            pins = [_wire(S[fn[s]], wr[s], wf[s], H, work.get("net_filter", True)) for s in range(fp[g], fp[g + 1])]
             def state(ix):
                 return sum(pins[j][ix] << j for j in range(k))
             y = [(truth[cell[g]] >> state(ix)) & 1 for ix in range(H + 2)]

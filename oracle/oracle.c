@@ -27,6 +27,16 @@
  *    narrower than the wire delay of its leading edge); otherwise a pin edge
  *    is scheduled at t + delay.
  *
+ *  - Interconnect without the filter (the paper's feature study, Section 5
+ *    and Table 7, deletes Algorithm 1's net-delay filtering lines and keeps
+ *    the wire delays): every net edge reaches the pin at t + delay, a
+ *    transport delay.  Only a pulse whose delayed trailing edge would arrive
+ *    no later than its delayed leading edge (possible when the rise and fall
+ *    wire delays differ) vanishes: the new arrival a = t + delay cancels the
+ *    arc's last scheduled pin edge when that edge is pending at a time
+ *    tp >= a, and is not scheduled itself.  (Several pin edges may then be
+ *    pending on one arc; the last scheduled one is the latest of them.)
+ *
  *  - Multiple simultaneous inputs (Algorithm 1, MSI resolution): all pin
  *    edges of a gate at the same time are applied first, then the gate is
  *    evaluated once by truth-table lookup (pin 0 is the least significant
@@ -365,6 +375,8 @@ static int32_t pin_state(const Design *d, const int32_t *pin_val, int32_t g)
  * probe_times[p*probe_cap ...].
  *
  * stats[0] += processed (non-cancelled) events, stats[1] += recorded edges.
+ * net_filter: 1 = the interconnect inertial filter, 0 = transport wire
+ * delays (the feature study's "no net delay" filtering).
  * Returns 0, or -1 on an internal inconsistency.
  */
 int32_t oracle_run(void *p, int32_t period, int32_t n_cycles,
@@ -373,7 +385,7 @@ int32_t oracle_run(void *p, int32_t period, int32_t n_cycles,
                    int64_t *tc, int64_t *t0, int64_t *t1, int64_t *ig, int64_t *ig_cycle,
                    int64_t *late_cycle, int32_t n_probe, const int32_t *probe_net, const int32_t *probe_cycle,
                    int32_t *probe_init, int32_t *probe_len, int32_t *probe_times, int32_t probe_cap,
-                   int64_t *stats)
+                   int64_t *stats, int32_t net_filter)
 {
     Design *d = (Design *)p;
     int32_t I = d->n_inputs, G = d->n_gates, N = d->n_nets;
@@ -455,8 +467,13 @@ int32_t oracle_run(void *p, int32_t period, int32_t n_cycles,
                     int32_t s = d->fo_slot[f];
                     int32_t g = d->slot_gate[s];
                     int64_t delta = v ? d->wire_r[s] : d->wire_f[s];
-                    if (arc_pend[s] >= 0 && ev.t < arc_pend_t[s]) {
-                        q.pool[arc_pend[s]].cancelled = 1;      /* pulse narrower than the wire delay */
+                    /* inertial: the net edge comes before the pending pin
+                     * edge matures; transport: the new arrival is no later
+                     * than the last scheduled, still pending one */
+                    int32_t cancel = arc_pend[s] >= 0 &&
+                                     (net_filter ? ev.t < arc_pend_t[s] : ev.t + delta <= arc_pend_t[s]);
+                    if (cancel) {
+                        q.pool[arc_pend[s]].cancelled = 1;      /* the pulse vanishes */
                         arc_pend[s] = -1;
                     } else {
                         int64_t pe = push(&q, ev.t + delta, d->level[I + g], EV_PIN, s, v);

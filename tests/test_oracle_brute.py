@@ -35,11 +35,14 @@ def _tiny(seed, wires, cond, zero, wide=False, edges=False):
 
 
 @pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "wide", "wide+wires+cond",
-                                  "edges+cond", "wide+wires+cond+edges"])
+                                  "edges+cond", "wide+wires+cond+edges", "transport-wires+cond",
+                                  "wide+transport-wires+cond+edges"])
 def test_oracle_matches_brute(mode):
     n_ok = 0
     for seed in range(1000, 1120):
         w = _tiny(seed, "wires" in mode, "cond" in mode, mode == "zero", wide="wide" in mode, edges="edges" in mode)
+        if "transport" in mode:
+            w["net_filter"] = False
         tc, t0, t1, waves = brute.simulate(w)
         N = len(tc)
         C = w["stimulus"]["n_cycles"]

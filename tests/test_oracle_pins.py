@@ -145,6 +145,42 @@ def test_wire_pulse_closed_form(init):
             assert times == []
 
 
+@pytest.mark.parametrize("init", [0, 1])
+def test_wire_transport_closed_form(init):
+    """Without the interconnect filter (the feature study's "no net delay",
+    Algorithm 1 with its net-delay filtering lines deleted) a wire is a
+    transport delay: a net pulse of width w whose leading edge takes d_l and
+    trailing edge d_t arrives as a pin pulse of width w + d_t - d_l, starting
+    at a + d_l, when that width is positive, and vanishes otherwise (a
+    delayed trailing edge no later than the delayed leading one).  A BUF
+    with unit delays behind it shifts the result by 1."""
+    cases = [(dl, dt, wdt) for dl in range(1, 11) for dt in range(1, 11) for wdt in range(1, 13)]
+    n = len(cases)
+    gates = [("BUF", [g]) for g in range(n)]
+    wires = [(dl, dt) if init == 0 else (dt, dl) for dl, dt, _ in cases]
+    w = work(n, gates, (1, 1), [[10, 10 + c[2]] for c in cases], [init] * n, period=100, wires=wires)
+    r = oracle.Oracle(w["netlist"], w["arcs"], w["wires"]).run(
+        w["stimulus"], probes=[(n + g, 0) for g in range(n)], net_filter=False)
+    for g, (dl, dt, wdt) in enumerate(cases):
+        _, times, _ = r["probes"][g]
+        if wdt + dt - dl > 0:
+            assert times == [11 + dl, 11 + wdt + dt], (init, dl, dt, wdt)
+        else:
+            assert times == [], (init, dl, dt, wdt)
+
+
+def test_wire_transport_keeps_every_pulse_in_flight():
+    """A transport wire longer than the gaps between its net's edges holds
+    several pin edges in flight at once; all of them arrive, shifted by the
+    wire delay, where the inertial filter keeps none of the narrow pulses."""
+    w = work(1, [("BUF", [0])], (1, 1), [[10, 20, 30, 45]], [0], period=200, wires=[(50, 50)])
+    o = oracle.Oracle(w["netlist"], w["arcs"], w["wires"])
+    r = o.run(w["stimulus"], probes=[(1, 0)], net_filter=False)
+    assert r["probes"][0][1] == [61, 71, 81, 96]
+    r = o.run(w["stimulus"], probes=[(1, 0)], net_filter=True)
+    assert r["probes"][0][1] == []
+
+
 def test_xor_glitch_generator():
     """One net through two buffers of delays a and b into an XOR2: a pulse
     of width |a-b| appears, filtered iff |a-b| is below the XOR's rise delay;
