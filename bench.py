@@ -363,28 +363,29 @@ def run_batch(args, torch, synth, G):
 
 
 def averaged_arcs(arcs):
-    """The same arcs with every conditional pair replaced by one
-    unconditional record carrying the pair's mean rise and fall (the
-    "averaged SDF" variant of the paper's feature study, Table 7)."""
-    g, p, cp = arcs["gate"], arcs["pin"], arcs["cond_pin"]
-    unc = cp < 0
+    """The same arcs with every pin whose delays carry qualifiers (condition
+    or input edge) reduced to one unconditional record with the mean rise and
+    fall of its records: the 2-element delay arrays of the paper's "no full
+    SDF" variant (Section 5, Table 7)."""
+    ie = arcs["in_edge"] if "in_edge" in arcs else np.zeros(len(arcs["gate"]), dtype=np.int8)
+    qual = (arcs["cond_pin"] >= 0) | (ie != 0)
     keys = {}
-    for i in np.nonzero(~unc)[0]:
-        keys.setdefault((int(g[i]), int(p[i])), []).append(i)
-    extra = sorted(keys.items())
-    out = {k: v[unc].copy() for k, v in arcs.items()}
-    add = {k: [] for k in arcs}
-    for (gg, pp), idx in extra:
+    for i in range(len(arcs["gate"])):
+        keys.setdefault((int(arcs["gate"][i]), int(arcs["pin"][i])), []).append(i)
+    keep, add = [], {k: [] for k in arcs}
+    for (gg, pp), idx in keys.items():
+        if not qual[idx].any():
+            keep.extend(idx)
+            continue
         add["gate"].append(gg)
         add["pin"].append(pp)
-        add["cond_pin"].append(-1)
-        add["cond_val"].append(0)
         add["rise"].append(int(round(float(np.mean(arcs["rise"][idx])))))
         add["fall"].append(int(round(float(np.mean(arcs["fall"][idx])))))
         for k in add:
             if len(add[k]) < len(add["gate"]):
-                add[k].append(0)                 # no other qualifier
-    return {k: np.concatenate([out[k], np.array(add[k], dtype=arcs[k].dtype)]) for k in arcs}
+                add[k].append(-1 if k == "cond_pin" else 0)     # no qualifier
+    keep = np.array(sorted(keep), dtype=np.int64)
+    return {k: np.concatenate([arcs[k][keep], np.array(add[k], dtype=arcs[k].dtype)]) for k in arcs}
 
 
 def run_features(args, torch, synth, G):
@@ -392,18 +393,28 @@ def run_features(args, torch, synth, G):
     study, Table 7): gate-eval time with conditional arcs (the benchmark's
     arcs), with them averaged away, with 10% of pins also carrying
     input-edge-qualified rows, with interconnect delays added, and with the
-    cycles run as continuous 16-cycle segments instead of one by one."""
+    cycles run as continuous 16-cycle segments instead of one by one.  The
+    Table 7 columns, with interconnect delays U{1..20} on every pin and
+    conditional plus input-edge-qualified arcs: full features, no net-delay
+    filter (transport wire delays), and no net-delay filter with every pin's
+    records averaged into one rise/fall pair (no full SDF)."""
     cycles = 2000
     w = synth.scale(n_cycles=cycles)
     net = w["netlist"]
-    variants = [("cond_arcs", w["arcs"], None, 1), ("averaged_arcs", averaged_arcs(w["arcs"]), None, 1),
-                ("cond_and_edge_arcs", synth.make_arcs(2, net, 5, 80, 0.10, edge_frac=0.10), None, 1),
-                ("cond_arcs_and_wires", w["arcs"], synth.make_wires(2, net, 1, 20), 1),
-                ("cond_arcs_segments16", w["arcs"], None, 16)]
+    wires = synth.make_wires(2, net, 1, 20)
+    full_arcs = synth.make_arcs(2, net, 5, 80, 0.10, edge_frac=0.10)
+    variants = [("cond_arcs", w["arcs"], None, 1, False), ("averaged_arcs", averaged_arcs(w["arcs"]), None, 1, False),
+                ("cond_and_edge_arcs", full_arcs, None, 1, False),
+                ("cond_arcs_and_wires", w["arcs"], wires, 1, False),
+                ("cond_arcs_segments16", w["arcs"], None, 16, False),
+                ("table7_full_features", full_arcs, wires, 1, False),
+                ("table7_no_net_delay", full_arcs, wires, 1, True),
+                ("table7_no_net_delay_no_full_sdf", averaged_arcs(full_arcs), wires, 1, True)]
     res = {}
-    for name, arcs, wires, seg in variants:
-        sim = G.GateSim(device=0, stream=torch.cuda.current_stream(), window_cycles=cycles, timing=True)
-        d, s = sim.load_work(dict(w, arcs=arcs, wires=wires))
+    for name, arcs, wires_v, seg, transport in variants:
+        sim = G.GateSim(device=0, stream=torch.cuda.current_stream(), window_cycles=cycles, timing=True,
+                        wire_transport=transport)
+        d, s = sim.load_work(dict(w, arcs=arcs, wires=wires_v))
         if seg > 1:
             s = sim.segment_stimulus(s, seg)
         sim.simulate(d, s, 0, cycles // seg)
@@ -455,7 +466,12 @@ def run_features(args, torch, synth, G):
             "cond_overhead": round(base / res["cond_arcs"] - 1, 4),
             "cond_and_edge_overhead": round(base / res["cond_and_edge_arcs"] - 1, 4),
             "segments16_overhead": round(base / res["cond_arcs_segments16"] - 1, 4),
-            "cond_and_wire_overhead": round(base / res["cond_arcs_and_wires"] - 1, 4)}
+            "cond_and_wire_overhead": round(base / res["cond_arcs_and_wires"] - 1, 4),
+            # the paper's Table 7 reading: extra kernel time of the full
+            # features over each reduced column
+            "table7_overhead_vs_no_net_delay": round(res["table7_no_net_delay"] / res["table7_full_features"] - 1, 4),
+            "table7_overhead_vs_no_net_delay_no_full_sdf":
+                round(res["table7_no_net_delay_no_full_sdf"] / res["table7_full_features"] - 1, 4)}
 
 
 def run_serve(args, torch, synth, G):

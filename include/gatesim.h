@@ -99,7 +99,12 @@ typedef struct {
     int32_t  autotune;        /* nonzero: gs_simulate_batch picks lds_cap, waves_per_block and tiles_per_wave by
                                  timing candidates on the batch, each job cut to 2,048 cycles (once per batch
                                  shape; another setting must beat the default by 3%) */
-    int32_t  reserved[5];
+    int32_t  wire_transport;  /* nonzero: interconnect delays without the net-delay filter (the paper's feature
+                                 study, Section 5, Table 7, deletes Algorithm 1's filtering lines and keeps the
+                                 delays): every net edge reaches the pin at its time plus the wire delay of its
+                                 direction, and a pulse vanishes only when its delayed trailing edge arrives no
+                                 later than its delayed leading edge; 0 = the inertial filter */
+    int32_t  reserved[4];
 } gs_options;
 
 /* Fills *opt with the defaults above. */

@@ -137,7 +137,7 @@ struct Seg {
     uint32_t gate_begin;
     uint32_t n_gates;
     uint32_t salt;                 // added to the block index to pick an arena stripe
-    uint32_t pad;
+    uint32_t mode;                 // bit 0: transport wire delays (no net-delay filter)
     WinView win;
     SaifAcc saif;
 };

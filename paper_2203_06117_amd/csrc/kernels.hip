@@ -555,6 +555,7 @@ struct Cursor {
     uint32_t idx[K], end[K];
     int32_t a[K];
     uint32_t state;
+    bool transport;                 // wire delays without the net-delay filter
 
     __device__ __forceinline__ int32_t word(int j, uint32_t i) const
     {
@@ -576,15 +577,20 @@ struct Cursor {
             return;
         }
         const int pv = (state >> j) & 1;
+        const int32_t d = pv ? arc.wf[j] : arc.wr[j];       // the net edge goes to !pv
+        const int32_t d1 = pv ? arc.wr[j] : arc.wf[j];      // the edge after it goes back to pv
+        // the pair is dropped when the second edge comes before the first
+        // arrives (inertial filter), or without the filter when the second
+        // arrives no later than the first (transport delay)
+        const int32_t thr = transport ? d - d1 + 1 : d;
         for (;;) {
             if (idx[j] >= end[j]) {
                 a[j] = kInf;
                 return;
             }
             const int32_t e0 = word(j, idx[j]);
-            const int32_t d = pv ? arc.wf[j] : arc.wr[j];   // the net edge goes to !pv
-            if (idx[j] + 1 < end[j] && word(j, idx[j] + 1) - e0 < d) {
-                idx[j] += 2;                                // pulse narrower than the wire delay
+            if (idx[j] + 1 < end[j] && word(j, idx[j] + 1) - e0 < thr) {
+                idx[j] += 2;                                // the pulse vanishes
                 continue;
             }
             a[j] = e0 + d;
@@ -680,12 +686,14 @@ __device__ __forceinline__ void walk(Cursor<K, WIRES, LDSRC> &P, const Arcs<K> &
 // lane's staged list of a pin, in place: walking the net's edges in order, an
 // edge followed by the next one sooner than the wire delay of the value it
 // goes to is dropped together with that next edge; every other edge becomes
-// a pin arrival at its time plus that delay.  v is the net's value before
-// the first edge.  On return [lo, hi) holds the arrivals.  Written without
-// branches: a lane writes behind its own read position only, and the word
-// read past its list (another lane's, or outside the stage) is never used.
+// a pin arrival at its time plus that delay.  With transport delays (the
+// filter deleted) a pair is dropped only when the next edge's arrival is no
+// later than this one's.  v is the net's value before the first edge.  On
+// return [lo, hi) holds the arrivals.  Written without branches: a lane
+// writes behind its own read position only, and the word read past its list
+// (another lane's, or outside the stage) is never used.
 __device__ __forceinline__ void wire_filter_lds(uint32_t base, uint32_t lo, uint32_t &hi, uint32_t v, int32_t wr,
-                                                int32_t wf)
+                                                int32_t wf, bool transport)
 {
     uint32_t r = lo, o = lo;
     while (r < hi) {
@@ -693,7 +701,9 @@ __device__ __forceinline__ void wire_filter_lds(uint32_t base, uint32_t lo, uint
         const int32_t e1 = gs_lds[base + r + 1];
         const uint32_t nv = v ^ 1u;
         const int32_t d = nv ? wr : wf;
-        const bool drop = r + 1 < hi && e1 - e0 < d;
+        const int32_t d1 = nv ? wf : wr;
+        const int32_t thr = transport ? d - d1 + 1 : d;
+        const bool drop = r + 1 < hi && e1 - e0 < thr;
         gs_lds[base + o] = e0 + d;
         o += drop ? 0u : 1u;
         r += drop ? 2u : 1u;
@@ -842,8 +852,8 @@ template <int K, bool WIRES, uint32_t GT>
 __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> &arc, uint64_t truth, uint32_t out_row,
                                               uint32_t tile_g, uint32_t ng, int lane, uint32_t lut_base,
                                               uint32_t out_base, uint32_t c_pos, const uint32_t (&ev)[K][GT / 2],
-                                              uint32_t salt, uint32_t &tc_sum, uint32_t &ig_sum, uint32_t &nact_sum,
-                                              int32_t &t1_lane)
+                                              uint32_t salt, bool transport, uint32_t &tc_sum, uint32_t &ig_sum,
+                                              uint32_t &nact_sum, int32_t &t1_lane)
 {
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;
@@ -936,10 +946,11 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
         }
         const uint32_t info = (uint32_t)gs_lds[qa + 3];
         P.state = (info >> 16) & 7u;
+        P.transport = transport;
         if (WIRES) {
 #pragma unroll
             for (int j = 0; j < K; j++)
-                wire_filter_lds(0, P.idx[j], P.end[j], (P.state >> j) & 1u, arc.wr[j], arc.wf[j]);
+                wire_filter_lds(0, P.idx[j], P.end[j], (P.state >> j) & 1u, arc.wr[j], arc.wf[j], transport);
         }
         int32_t cnt;
         walk_lds_c<K>(P, (int)((info >> 19) & 1u), lut_base, info & 0xffffu, cnt);
@@ -1066,6 +1077,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
 {
     constexpr uint32_t GT = K <= 3 ? 4 : 2;
     const WinView &win = sg.win;
+    const bool transport = (sg.mode & 1u) != 0;
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;
     Arcs<K> arc;
@@ -1210,7 +1222,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         if constexpr (K <= 3) {
             if (try_compact) {
                 if (compact_group<K, WIRES, GT>(win, arc, g.truth, out_row, tile0 + gb, ng, lane, lut_base, out_base,
-                                                c_pos, ev, sg.salt, tc_sum, ig_sum, nact_sum, t1_lane))
+                                                c_pos, ev, sg.salt, transport, tc_sum, ig_sum, nact_sum, t1_lane))
                     continue;
                 // too many lanes with two or more events: the per-tile walk
                 if (lane == 0) {
@@ -1248,9 +1260,11 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     P.end[j] = hi[j];
                     // with interconnect delays, each staged net list becomes
                     // the pin's arrival list first
-                    if (WIRES) wire_filter_lds(base[j], lo[j], P.end[j], (state0 >> j) & 1u, arc.wr[j], arc.wf[j]);
+                    if (WIRES)
+                        wire_filter_lds(base[j], lo[j], P.end[j], (state0 >> j) & 1u, arc.wr[j], arc.wf[j], transport);
                 }
                 P.state = state0;
+                P.transport = transport;
                 walk_lds<K, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, cnt);
             } else {
                 Cursor<K, WIRES, false> P;
@@ -1261,6 +1275,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     P.end[j] = hi[j];
                 }
                 P.state = state0;
+                P.transport = transport;
                 walk<K, WIRES, false, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
             }
 
@@ -1332,6 +1347,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                         P.end[j] = hi[j];
                     }
                     P.state = state0;
+                    P.transport = transport;
                     int32_t c2, z2;
                     walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, ok ? cnt : 0, c2, acc,
                                                   z2);

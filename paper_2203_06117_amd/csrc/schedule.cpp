@@ -79,7 +79,6 @@ void build_steps(gs_ctx *ctx, const std::vector<Piece> &pieces, const std::vecto
                  std::vector<Seg> &segs, std::vector<size_t> &step_off, std::vector<size_t> &step_n,
                  std::vector<uint64_t> &step_waves, std::vector<int32_t> &step_kmax, std::vector<int32_t> &step_wires)
 {
-    (void)ctx;
     int32_t maxL = 0;
     for (const Piece &p : pieces) maxL = std::max(maxL, p.d->L);
     uint64_t salt = 0;
@@ -102,6 +101,7 @@ void build_steps(gs_ctx *ctx, const std::vector<Piece> &pieces, const std::vecto
             g.gate_begin = p.d->level_ptr[l];
             g.n_gates = n_gates;
             g.salt = (uint32_t)salt;
+            g.mode = ctx->opt.wire_transport ? 1u : 0u;
             g.win = views[i];
             g.saif = saif_view(p.d->d_stage, (size_t)p.d->N);
             const uint64_t nw = (uint64_t)n_gates * ngroup;

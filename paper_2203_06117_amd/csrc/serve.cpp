@@ -503,6 +503,7 @@ gs_status launch_step(gs_ctx *ctx, ServeState *S, std::vector<ReqP> &run, std::s
         g.gate_begin = q->lvl_begin[q->next];
         g.n_gates = q->lvl_n[q->next];
         g.salt = (uint32_t)S->salt;
+        g.mode = ctx->opt.wire_transport ? 1u : 0u;
         g.win = q->view;
         g.saif = q->acc;
         const uint64_t nw = (uint64_t)g.n_gates * ngroup;

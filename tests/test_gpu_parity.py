@@ -98,7 +98,8 @@ def test_pulse_grid(G, cell):
     assert_same(w, got, oracle.simulate(w), cell)
 
 
-@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "multi-edge", "wires+cond+edges"])
+@pytest.mark.parametrize("mode", ["plain", "wires", "cond", "wires+cond", "zero", "multi-edge", "wires+cond+edges",
+                                  "transport-wires", "transport-wires+cond+edges"])
 def test_random_small(G, mode):
     for seed in range(20):
         rng = np.random.default_rng(seed + 100)
@@ -111,10 +112,13 @@ def test_random_small(G, mode):
                                float(rng.uniform(0.05, 0.6)), 0 if zero else 1, 0 if zero else int(rng.integers(2, 80)),
                                cond_frac=0.3 if "cond" in mode else 0.0,
                                wire=(1, int(rng.integers(1, 25))) if "wires" in mode else None,
-                               extra=3 if mode in ("multi-edge", "wires") else 0, extra_p=0.3,
+                               extra=3 if mode in ("multi-edge", "wires", "transport-wires") else 0, extra_p=0.3,
                                skew=min(50, T - 1), edge_frac=0.4 if "edges" in mode else 0.0)
+        transport = "transport" in mode
+        if transport:
+            w["net_filter"] = False
         say("random", mode, seed, gates, levels, C, T)
-        got = gpu_saif(G, w, window_cycles=int(rng.choice([0, 64, 100, 37])))
+        got = gpu_saif(G, w, window_cycles=int(rng.choice([0, 64, 100, 37])), wire_transport=transport)
         assert_same(w, got, oracle.simulate(w), f"{mode} seed {seed}")
 
 
@@ -285,6 +289,22 @@ def test_invariance(G, opt):
     assert_same(w, got, oracle.simulate(w), str(opt))
     if opt.get("hbm_budget"):
         assert got[4]["window_retries"] > 0
+
+
+def test_transport_wires_dense(G):
+    """Wire delays without the net-delay filter on inputs with several
+    toggles per cycle: the per-tile walk from the arena (unstaged groups),
+    its spill path, and the staged paths all keep every pulse whose delayed
+    width is positive."""
+    w = synth.small_random(78, 600, 16, 12, 200, 2000, 0.9, 2, 60, cond_frac=0.2, extra=6, extra_p=0.9,
+                           wire=(1, 40), edge_frac=0.3)
+    w["net_filter"] = False
+    ref = oracle.simulate(w)
+    for opt in (dict(lds_cap=8), dict(tiles_per_wave=2, lds_cap=4), dict()):
+        say("transport dense", opt)
+        got = gpu_saif(G, w, wire_transport=True, **opt)
+        assert_same(w, got, ref, f"transport dense {opt}")
+        assert got[4]["unstaged_groups"] > 0
 
 
 def test_dense_activity(G):
