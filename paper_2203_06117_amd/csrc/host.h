@@ -63,10 +63,9 @@ struct Design {
     uint64_t version = 0;
     // learned from earlier rounds, used for performance only: transition
     // words per net and picosecond of lane time in the last round that ran
-    // this design alone (a segment view's lanes are longer), and the window
-    // length a full arena last forced (0 = none)
+    // this design alone (a segment view's lanes are longer); the window
+    // planner and the arena guess size windows from it
     double words_per_ps = 0;
-    int32_t window_fit = 0;
     // device
     int64_t *d_fanin_ptr = nullptr;
     int32_t *d_fanin_net = nullptr;

@@ -85,7 +85,8 @@ struct WinView {
     ChunkHdr *hdr;
     uint16_t *ends;
     int32_t *times;
-    unsigned long long *bump;      // one counter per stripe, kBumpStride apart: words handed out in the stripe
+    unsigned long long *bump;      // per stripe, kBumpStride apart: [0] words taken from the stripe (by handed-out
+                                   // reservations and failed tries), [1] words of failed tries
     unsigned int *flags;           // [0] arena full, [1] chunk over kMaxChunk, [2] spilled lanes, [3] bound violated,
                                    // [4] tile groups walked from the arena (too many words to stage),
                                    // [5] staged groups whose multi-event lanes overflowed the compacted queue

@@ -289,6 +289,39 @@ hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n
 }
 
 // --------------------------------------------------------------------------
+// Arena reservation.  A wave reserves the words of its output chunks with
+// one atomic on its stripe's counter.  When that stripe is full, a few other
+// stripes spread over the arena are tried before the round is flagged for a
+// retry (flags[0]), so one full stripe does not fail a round while others
+// have room.  A failed try leaves its counter past the stripe's end (taking
+// the words back could hand one range out twice while other waves reserve)
+// and adds its words to the stripe's second counter, so that the host can
+// tell the words handed out from the words lost to failed tries.  Returns
+// the reservation's first word, counted from the window's `times`, or ~0
+// when no try succeeded.
+// --------------------------------------------------------------------------
+constexpr uint32_t kStripeTries = 4;
+
+__device__ __forceinline__ uint64_t arena_reserve(const WinView &win, uint32_t stripe0, uint32_t n, int lane)
+{
+    for (uint32_t k = 0; k < kStripeTries; k++) {
+        const uint32_t s = (stripe0 + k * 97u) & win.stripe_mask;
+        uint64_t b = 0;
+        if (lane == 0)
+            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)s * kBumpStride), (unsigned long long)n,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b = uniform64(b);
+        if (b + n <= win.slice_words) return win.arena_off + (uint64_t)s * win.slice_words + b;
+        if (lane == 0)
+            __hip_atomic_fetch_add(glob(win.bump + (size_t)s * kBumpStride + 1), (unsigned long long)n,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (win.stripe_mask == 0) break;
+    }
+    if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return ~0ull;
+}
+
+// --------------------------------------------------------------------------
 // Stimulus expansion (the input restructuring GATSPI does before its
 // kernels, Section 4): absolute toggle times of input i become the
 // (input, tile) chunks of the window, in cycle-local time, with every
@@ -364,19 +397,12 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
 
     // one arena reservation for the group's chunks
     const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
-    uint64_t b = 0;
+    uint64_t base = 0;
     bool ok = true;
     if (n > 0) {
-        if (lane == 0)
-            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)n,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        b = uniform64(b);
-        if (b + n > win.slice_words) {
-            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-        }
+        base = arena_reserve(win, stripe, n, lane);
+        ok = base != ~0ull;
     }
-    const uint64_t base = win.arena_off + (uint64_t)stripe * win.slice_words + b;
     // toggles, one per lane and row: cycle index (group-relative), local time,
     // the T1 term of the edge, and the group's output word
     const double inv_t = 1.0 / (double)T;
@@ -984,19 +1010,13 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
 
     // one reservation for the group's output chunks, exactly their words
     const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
-    uint64_t wb = 0;
+    uint64_t wbase = 0;
     bool ok = true;
     if (R > 0) {
-        if (lane == 0)
-            wb = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)R,
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wb = uniform64(wb);
-        if (wb + R > win.slice_words) {
-            if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-        }
+        wbase = arena_reserve(win, stripe, R, lane);
+        ok = wbase != ~0ull;
+        if (!ok) wbase = 0;
     }
-    const uint64_t wbase = win.arena_off + (uint64_t)stripe * win.slice_words + wb;
     int32_t *out = win.times + wbase;
 
     // 3b. lane ends, headers, single edges; queued lanes learn their place
@@ -1148,24 +1168,17 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 ev[j][u / 2] = ld_u16(r0, (uint32_t)lane) | (ld_u16(r1, (uint32_t)lane) << 16);
             }
         }
-        // The group's output chunks get one arena reservation: a lane's
-        // output never has more edges than its pins have events (Algorithm 1
-        // appends at most one edge per event), so the fanin totals bound it.
+        // The group's fanin words (the stage size it needs): a lane's output
+        // never has more edges than its pins have events (Algorithm 1
+        // appends at most one edge per event), so they also bound its output.
         const uint32_t c_incl = wave_incl_scan(c_tot);
         const uint32_t bound = (uint32_t)lane63(c_incl);
         const uint32_t c_pos = stage_base + wave_shr1(c_incl);  // chunk's first word in the LDS stage
-        // (the returned offset is first needed after the walk of the first tile)
         const uint32_t stripe = (blockIdx.x + sg.salt) & win.stripe_mask;
         const bool staged = bound <= kStageWords;
         // staged groups of gates with up to three pins take the compacted
         // path, which reserves exactly its output words later
         const bool try_compact = K <= 3 && staged;
-        uint64_t bres = 0;
-        if (!try_compact && bound > 0 && lane == 0)
-            bres = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride), (unsigned long long)bound,
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t wbase = 0;
-        bool wok = true, placed = false;
         if (!staged && lane == 0)                               // counted for the statistics
             __hip_atomic_fetch_add(glob(win.flags + 4), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // A producing wave places the chunks of its tile group one after
@@ -1225,14 +1238,12 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                                                 c_pos, ev, sg.salt, transport, tc_sum, ig_sum, nact_sum, t1_lane))
                     continue;
                 // too many lanes with two or more events: the per-tile walk
-                if (lane == 0) {
+                if (lane == 0)
                     __hip_atomic_fetch_add(glob(win.flags + 5), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    bres = __hip_atomic_fetch_add(glob(win.bump + (size_t)stripe * kBumpStride),
-                                                  (unsigned long long)bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
             }
         }
-        uint32_t used = 0;                                      // words of the reservation handed out
+        // the per-tile walk: each tile's output chunk reserves exactly its
+        // words once the tile's lane counts are known
         for (uint32_t u = 0; u < ng; u++) {
             const uint32_t tile = tile0 + gb + u;
             const int32_t lc = (int32_t)(tile * kLanes) + lane;
@@ -1279,32 +1290,22 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 walk<K, WIRES, false, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
             }
 
-            if (!placed) {
-                placed = true;
-                const uint64_t b = uniform64(bres);
-                if (bound > 0 && b + bound > win.slice_words) {
-                    if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    wok = false;
-                }
-                wbase = win.arena_off + (uint64_t)stripe * win.slice_words + b;
-            }
             const uint32_t ucnt = (uint32_t)cnt;
             const uint32_t incl = wave_incl_scan(ucnt);
             const uint32_t total = (uint32_t)lane63(incl);
             const uint64_t mask = __ballot(active && y0);
             const uint64_t ci = (uint64_t)out_row * ntile + tile;
-            bool ok = wok;
+            bool ok = true;
             if (total > kMaxChunk) {
                 if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = false;
             }
-            if (used + total > bound) {                    // cannot happen (bound above); never write past it
-                if (lane == 0) __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = false;
+            uint64_t obase = 0;
+            if (ok && total > 0) {
+                obase = arena_reserve(win, stripe, total, lane);
+                ok = obase != ~0ull;
+                if (!ok) obase = 0;
             }
-            ok = uniform(ok ? 1u : 0u) != 0;
-            const uint64_t obase = wbase + used;
-            if (ok) used += total;
             st_u16(win.ends + ci * kLanes, (uint32_t)lane,
                    (uint16_t)((ok ? incl : 0u) | ((active && y0) ? 1u << kEndInitShift : 0u)));
             if (lane == 0) {

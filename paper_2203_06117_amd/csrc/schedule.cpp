@@ -279,7 +279,9 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     }
     const WinView &v0 = views.front();
     uint64_t used = 0;
-    for (uint32_t i = 0; i <= v0.stripe_mask; i++) used += std::min<uint64_t>(hb[(size_t)i * kBumpStride], v0.slice_words);
+    // words handed out: each stripe's counter less the words of its failed tries
+    for (uint32_t i = 0; i <= v0.stripe_mask; i++)
+        used += std::min<uint64_t>(hb[(size_t)i * kBumpStride] - hb[(size_t)i * kBumpStride + 1], v0.slice_words);
     ctx->stats.arena_words = (int64_t)used;
     ctx->stats.spilled_lanes += f32[2];
     ctx->stats.unstaged_groups += f32[4];
@@ -291,7 +293,7 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
         ctx->stats.window_retries++;
         return GS_OK;
     }
-    if (ctx->d_profile || ctx->d_late)
+    if (commit && (ctx->d_profile || ctx->d_late))          // rounds that add nothing (pilots, trials) are not profiled
         for (const Piece &p : pieces) {
             const int64_t at = p.c0 - ctx->profile_begin;
             HIPCHK(launch_cycle_profile(ctx->win.ends + p.chunk_base * kLanes, ctx->win.hdr + p.chunk_base,
@@ -332,7 +334,7 @@ uint64_t piece_arena_guess(const Piece &p)
 // is retried with twice the arena; at the budget limit the round is split
 // and, for a single piece, its window is halved.
 gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, bool commit, bool timing,
-                     double *gate_eval_ms)
+                     double *gate_eval_ms, uint64_t min_words = 0)
 {
     std::reverse(pending.begin(), pending.end());      // pop from the back in submission order
     uint64_t grown = 0;
@@ -367,7 +369,7 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
             return gs_fail(ctx, GS_E_NOMEM, "budget cannot hold the chunk headers of one window");
         }
         const uint64_t max_words = (ctx->budget - hdr) / sizeof(int32_t);
-        uint64_t words = std::min(max_words, std::max(guess, std::max(grown, ctx->win.words)));
+        uint64_t words = std::min(max_words, std::max(std::max(guess, min_words), std::max(grown, ctx->win.words)));
         RoundResult rr;
         gs_status st = run_round(ctx, round, words, tu, commit, timing, rr);
         if (st) return st;
@@ -384,7 +386,6 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
         } else if (round[0].cycles > kLanes) {
             Piece p = round[0], a = p, b = p;
             a.cycles = p.cycles / 2;
-            p.d->window_fit = a.cycles;                       // later calls start at this length
             a.tiles = (a.cycles + kLanes - 1) / kLanes;
             b.c0 = p.c0 + a.cycles;
             b.cycles = p.cycles - a.cycles;
@@ -412,13 +413,24 @@ Piece make_piece(gs_ctx *ctx, int32_t di, int32_t si, int32_t c0, int32_t cycles
     return p;
 }
 
-int32_t default_window(gs_ctx *ctx, const Design *d)
+// Window length for a design and a stimulus period: the caller's, else the
+// longest power-of-two number of cycles up to 16,384 whose chunk headers
+// take at most a third of the budget and, once the design's transition
+// density is known, whose headers and transitions (with 15% to spare) fit
+// the budget.
+int32_t default_window(gs_ctx *ctx, const Design *d, int32_t period)
 {
     int32_t W = ctx->opt.window_cycles;
     if (W <= 0) {
         W = 16384;
         while (W > kLanes && gs_header_bytes(d->N, W) * 3 > ctx->budget) W /= 2;
-        if (d->window_fit > 0) W = std::min(W, d->window_fit);    // a full arena forced this length before
+        if (d->words_per_ps > 0) {
+            auto need = [&](int32_t w) {
+                return (double)gs_header_bytes(d->N, w) +
+                       d->words_per_ps * (double)period * 1.15 * (double)d->N * (double)w * sizeof(int32_t);
+            };
+            while (W > kLanes && need(W) > (double)ctx->budget) W /= 2;
+        }
     }
     return W;
 }
@@ -520,7 +532,18 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
     const uint64_t t_start = gs_now_ns();
     ctx->last = LastWindow();
     Design *d = ctx->designs[design];
-    const int32_t W = default_window(ctx, d);
+    // a design's first run learns its transition density from a 64-cycle
+    // pilot (nothing committed), so that the arena of the real windows is
+    // sized from it rather than guessed and retried
+    if (d->words_per_ps <= 0 && cycle_end - cycle_begin > 2 * kLanes) {
+        const Piece pilot = make_piece(ctx, design, stim, cycle_begin, kLanes);
+        // room for 8 transitions per (net, cycle), so that the pilot itself
+        // rarely needs a second try
+        st = run_pieces(ctx, std::vector<Piece>{pilot}, tuning_for(ctx, {pilot}), false, false, nullptr,
+                        8ull * (uint64_t)d->N * kLanes);
+        if (st) return st;
+    }
+    const int32_t W = default_window(ctx, d, ctx->stims[stim]->period);
     std::vector<Piece> pieces;
     for (int32_t c0 = cycle_begin; c0 < cycle_end; c0 += W)
         pieces.push_back(make_piece(ctx, design, stim, c0, std::min(W, cycle_end - c0)));
@@ -539,8 +562,8 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
 // the segment table, then the window (chunk headers, lane ends, transition
 // arena, carved as for a caller-owned arena).  Windows are as long as the
 // headers fit in half of the window region; a full arena halves them.  The
-// context's own buffers, options and learned window length are restored on
-// return.  Calls that overlap on one GPU share the scratch and race.
+// context's own buffers and options are restored on return.  Calls that
+// overlap on one GPU share the scratch and race.
 extern "C" gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin,
                                          int32_t cycle_end)
 {
@@ -576,9 +599,8 @@ extern "C" gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t st
         size_t segs_cap;
         int32_t *c0;
         size_t c0_cap;
-        int32_t window_fit;
     } sv{ctx->opt, ctx->budget, ctx->win, ctx->d_misc, ctx->d_bump, ctx->d_segs, ctx->segs_cap, ctx->d_c0,
-         ctx->c0_cap, d->window_fit};
+         ctx->c0_cap};
     ctx->opt.arena = win;
     ctx->opt.arena_bytes = win_bytes;
     ctx->opt.schedule = GS_SCHED_LEVELS;
@@ -608,7 +630,6 @@ extern "C" gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t st
     ctx->segs_cap = sv.segs_cap;
     ctx->d_c0 = sv.c0;
     ctx->c0_cap = sv.c0_cap;
-    d->window_fit = sv.window_fit;
     ctx->last = LastWindow();                  // the scratch window is not kept for gs_read_waveform
     ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
     return st;
@@ -694,7 +715,7 @@ extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job
     for (int32_t i = 0; i < n_jobs; i++) {
         const gs_job &j = jobs[i];
         Design *d = ctx->designs[j.design];
-        const int32_t W = default_window(ctx, d);
+        const int32_t W = default_window(ctx, d, ctx->stims[j.stim]->period);
         for (int32_t c0 = j.cycle_begin; c0 < j.cycle_end; c0 += W)
             pieces.push_back(make_piece(ctx, j.design, j.stim, c0, std::min(W, j.cycle_end - c0)));
     }

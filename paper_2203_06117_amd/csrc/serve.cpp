@@ -687,7 +687,8 @@ void serve_loop(gs_ctx *ctx, ServeState *S)
             } else {
                 uint64_t used = 0;
                 for (uint32_t st2 = 0; st2 <= q->view.stripe_mask; st2++)
-                    used += std::min<uint64_t>(hb[(size_t)st2 * kBumpStride], q->view.slice_words);
+                    used += std::min<uint64_t>(hb[(size_t)st2 * kBumpStride] - hb[(size_t)st2 * kBumpStride + 1],
+                                               q->view.slice_words);
                 const double rows = q->r.kind == GS_REQ_EDIT ? std::max<uint32_t>(q->n_cone, 1) : q->d->N;
                 const double wpc = (double)used / (rows * q->cycles);
                 double &est = S->words_per_net_cycle[q->d];

@@ -340,6 +340,22 @@ def test_queue_overflow(G):
                 assert got[4]["queue_overflows"] > 0
 
 
+def test_exact_arena(G):
+    """Output chunks reserve exactly their words on every path (compacted
+    groups, the per-tile walk of unstaged and overflowing groups, stimulus
+    expansion): one window's arena use equals the window's transitions."""
+    w = synth.small_random(79, 3000, 40, 30, 512, 1500, 0.9, 2, 60, cond_frac=0.2, extra=6, extra_p=0.9,
+                           edge_frac=0.3)
+    ref = oracle.simulate(w)
+    for opt in (dict(window_cycles=512), dict(window_cycles=512, tiles_per_wave=1), dict(window_cycles=512,
+                                                                                         lds_cap=4)):
+        say("exact arena", opt)
+        got = gpu_saif(G, w, **opt)
+        assert_same(w, got, ref, f"exact arena {opt}")
+        assert got[4]["unstaged_groups"] > 0
+        assert got[4]["arena_words"] == int(ref["tc"].sum()), (got[4]["arena_words"], int(ref["tc"].sum()))
+
+
 def test_learned_density(G):
     """A design whose logic multiplies its inputs' toggles (ripple-carry-like
     XOR/MUX chains, about 1.07 transitions per net and cycle from 0.3 input
