@@ -21,16 +21,37 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A test may point the oracle at another build of oracle.c (a sanitizer
+# build, or a deliberately broken copy that the pins must reject).
+_LIB_OVERRIDE = os.environ.get("GATESIM_ORACLE_LIB")
 _lib = None
+
+GCC_FLAGS = ["-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared"]
+# AddressSanitizer and UndefinedBehaviorSanitizer, every report fatal; the
+# library is loaded into an unsanitized Python, so the ASan runtime must be
+# preloaded (asan_runtime()) and leak checks stay off
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
+
+
+def compile_oracle(src: str, out: str, sanitize: bool = False) -> str:
+    """Compile an oracle source file with gcc into the shared library out."""
+    flags = GCC_FLAGS + (SANITIZE_FLAGS if sanitize else [])
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc"] + flags + [src, "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
+def asan_runtime() -> str:
+    """Path of gcc's AddressSanitizer runtime (for LD_PRELOAD)."""
+    return subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
-                               _SRC, "-o", tmp])
-        os.replace(tmp, _LIB)
+        compile_oracle(_SRC, _LIB)
     return _LIB
 
 
@@ -38,9 +59,10 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    path = _LIB_OVERRIDE or _LIB
+    if not _LIB_OVERRIDE and not os.path.exists(_LIB):
         build(force=True)
-    lib = C.CDLL(_LIB)
+    lib = C.CDLL(path)
     P = C.c_void_p
     lib.oracle_new.restype = P
     lib.oracle_new.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P,
