@@ -226,6 +226,7 @@ def run_scale(args, torch, synth, GateSim):
         "transitions_per_gate_cycle": round(a_bar, 4),
         "glitch_share_of_gate_toggles": round(glitch_share, 4),
         "spilled_lanes": st["spilled_lanes"],
+        "unstaged_groups": st["unstaged_groups"], "queue_overflows": st["queue_overflows"],
         "window_retries": st["window_retries"],
         "roofline": roofline,
         "cpu_baseline": cpu,

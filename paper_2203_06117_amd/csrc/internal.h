@@ -22,10 +22,11 @@ constexpr uint32_t kStageWords = 512;
 // Compacted evaluation of a staged tile group: a lane never has more output
 // edges than pin events, so the group's output edges fit a stage of the
 // same size; lanes with two or more pin events are queued (up to
-// kQueueCap of them, kQueueWords words each) and walked together.
+// kQueueCap of them, one word per pin, at most kQueueWords) and walked
+// together.
 constexpr uint32_t kOutStageWords = kStageWords;
-constexpr uint32_t kQueueCap = 128;
-constexpr uint32_t kQueueWords = 4;
+constexpr uint32_t kQueueCap = 192;
+constexpr uint32_t kQueueWords = 3;
 
 // LDS words of one gate-evaluation wave: the delay table (64 words), the
 // fanin stage, then a region shared by the per-lane output slots of the

@@ -304,8 +304,11 @@ constexpr uint32_t kStripeTries = 4;
 
 __device__ __forceinline__ uint64_t arena_reserve(const WinView &win, uint32_t stripe0, uint32_t n, int lane)
 {
+    uint32_t s = stripe0;
+    // the first try inline; the rare further tries in a loop kept rolled,
+    // so that the common path carries no extra registers
+#pragma nounroll
     for (uint32_t k = 0; k < kStripeTries; k++) {
-        const uint32_t s = (stripe0 + k * 97u) & win.stripe_mask;
         uint64_t b = 0;
         if (lane == 0)
             b = __hip_atomic_fetch_add(glob(win.bump + (size_t)s * kBumpStride), (unsigned long long)n,
@@ -316,6 +319,7 @@ __device__ __forceinline__ uint64_t arena_reserve(const WinView &win, uint32_t s
             __hip_atomic_fetch_add(glob(win.bump + (size_t)s * kBumpStride + 1), (unsigned long long)n,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (win.stripe_mask == 0) break;
+        s = (s + 97u) & win.stripe_mask;
     }
     if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return ~0ull;
@@ -884,6 +888,7 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;
     const uint32_t queue = out_base + kOutStageWords;
+    const uint32_t stage_base = out_base - kStageWords;
     uint64_t mmask[GT];           // lanes queued in tile u
     uint32_t qbase[GT];           // their first queue entry
     int32_t e1[GT];               // a single-event lane's output edge
@@ -944,10 +949,17 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
             if (qn + nm > kQueueCap) return false;
             if (multi) {
                 const uint32_t q = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
-                const uint32_t qa = queue + q * kQueueWords;
+                const uint32_t qa = queue + q * (uint32_t)K;
+                // K words: pin j's list as stage-relative [start, end) in
+                // bits 0-9 and 10-19; word 0 also carries the lane's output
+                // region (from out_base) and its pin state in bits 20-31
 #pragma unroll
-                for (int j = 0; j < K; j++) gs_lds[qa + j] = (int32_t)(pos[j] | ((pos[j] + nj[j]) << 16));
-                gs_lds[qa + 3] = (int32_t)((out_base + tileoff + lsum) | (st0 << 16) | (y0 << 19));
+                for (int j = 0; j < K; j++) {
+                    const uint32_t r = pos[j] - stage_base;
+                    uint32_t w = r | ((r + nj[j]) << 10);
+                    if (j == 0) w |= ((tileoff + lsum) | (st0 << 9)) << 20;
+                    gs_lds[qa + j] = (int32_t)w;
+                }
             }
             mmask[u] = mm;
             qn += nm;
@@ -961,17 +973,18 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
     for (uint32_t qb = 0; qb < qn; qb += kLanes) {
         const uint32_t q = qb + (uint32_t)lane;
         const bool valid = q < qn;
-        const uint32_t qa = queue + min(q, qn - 1) * kQueueWords;
+        const uint32_t qa = queue + min(q, qn - 1) * (uint32_t)K;
         Cursor<K, false, true> P;
+        uint32_t info = 0;
 #pragma unroll
         for (int j = 0; j < K; j++) {
             const uint32_t w = (uint32_t)gs_lds[qa + j];
+            if (j == 0) info = w >> 20;
             P.base[j] = 0;
-            P.idx[j] = w & 0xffffu;
-            P.end[j] = valid ? w >> 16 : P.idx[j];
+            P.idx[j] = stage_base + (w & 0x3ffu);
+            P.end[j] = valid ? stage_base + ((w >> 10) & 0x3ffu) : P.idx[j];
         }
-        const uint32_t info = (uint32_t)gs_lds[qa + 3];
-        P.state = (info >> 16) & 7u;
+        P.state = (info >> 9) & 7u;
         P.transport = transport;
         if (WIRES) {
 #pragma unroll
@@ -979,8 +992,8 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
                 wire_filter_lds(0, P.idx[j], P.end[j], (P.state >> j) & 1u, arc.wr[j], arc.wf[j], transport);
         }
         int32_t cnt;
-        walk_lds_c<K>(P, (int)((info >> 19) & 1u), lut_base, info & 0xffffu, cnt);
-        if (valid) gs_lds[qa] = cnt;
+        walk_lds_c<K>(P, (int)((truth >> ((info >> 9) & 7u)) & 1u), lut_base, out_base + (info & 0x1ffu), cnt);
+        if (valid) gs_lds[qa] = (int32_t)((info << 20) | (uint32_t)cnt);       // count in bits 0-9
     }
     wave_lds_sync();
 
@@ -998,7 +1011,7 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
             uint32_t c = (bits >> u) & 1u;
             if (multi) {
                 const uint32_t q = qbase[u] + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
-                c = (uint32_t)gs_lds[queue + q * kQueueWords];
+                c = (uint32_t)gs_lds[queue + q * (uint32_t)K] & 0x3ffu;
             }
             incl[u] = wave_incl_scan(c);
             tot[u] = (uint32_t)lane63(incl[u]);
@@ -1045,7 +1058,8 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
             const bool multi = (mm >> lane) & 1u;
             if (multi) {
                 const uint32_t q = qbase[u] + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
-                gs_lds[queue + q * kQueueWords + 1] = (int32_t)first;
+                const uint32_t a = queue + q * (uint32_t)K;
+                gs_lds[a] = (int32_t)(((uint32_t)gs_lds[a] & 0xfff003ffu) | (first << 10));   // first word in bits 10-19
             } else if (active) {
                 // T1 of the cycle: the settled value over [0, T), or up to
                 // the single edge and the new value after it
@@ -1063,12 +1077,11 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
     for (uint32_t qb = 0; qb < qn; qb += kLanes) {
         const uint32_t q = qb + (uint32_t)lane;
         const bool valid = q < qn;
-        const uint32_t qa = queue + min(q, qn - 1) * kQueueWords;
-        const int32_t c = valid ? gs_lds[qa] : 0;
-        const uint32_t first = (uint32_t)gs_lds[qa + 1];
-        const uint32_t info = (uint32_t)gs_lds[qa + 3];
-        const uint32_t opos = info & 0xffffu;
-        int v = (int)((info >> 19) & 1u);
+        const uint32_t w0 = (uint32_t)gs_lds[queue + min(q, qn - 1) * (uint32_t)K];
+        const int32_t c = valid ? (int32_t)(w0 & 0x3ffu) : 0;
+        const uint32_t first = (w0 >> 10) & 0x3ffu;
+        const uint32_t opos = out_base + ((w0 >> 20) & 0x1ffu);
+        int v = (int)((truth >> ((w0 >> 29) & 7u)) & 1u);
         int32_t s1 = 0;
         for (int32_t i = 0; i < c; i++) {
             const int32_t e = gs_lds[opos + (uint32_t)i];
@@ -1242,8 +1255,18 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     __hip_atomic_fetch_add(glob(win.flags + 5), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        // the per-tile walk: each tile's output chunk reserves exactly its
-        // words once the tile's lane counts are known
+        // the per-tile walk.  A staged group (at most kStageWords fanin
+        // words, which bound its output) reserves that bound at once, so the
+        // atomic's latency overlaps the walk; an unstaged group, where
+        // activity is dense and memory matters, reserves each tile's exact
+        // words once the tile's lane counts are known.
+        uint64_t gbase = 0;                                     // staged: the group's reservation
+        bool gok = true;
+        uint32_t used = 0;                                      // staged: its words handed out
+        if (staged && bound > 0) {
+            gbase = arena_reserve(win, stripe, bound, lane);
+            gok = gbase != ~0ull;
+        }
         for (uint32_t u = 0; u < ng; u++) {
             const uint32_t tile = tile0 + gb + u;
             const int32_t lc = (int32_t)(tile * kLanes) + lane;
@@ -1301,7 +1324,11 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 ok = false;
             }
             uint64_t obase = 0;
-            if (ok && total > 0) {
+            if (staged) {
+                ok = ok && gok && used + total <= bound;       // the bound holds: never write past it
+                obase = ok ? gbase + used : 0;
+                if (ok) used += total;
+            } else if (ok && total > 0) {
                 obase = arena_reserve(win, stripe, total, lane);
                 ok = obase != ~0ull;
                 if (!ok) obase = 0;

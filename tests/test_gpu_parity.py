@@ -341,9 +341,11 @@ def test_queue_overflow(G):
 
 
 def test_exact_arena(G):
-    """Output chunks reserve exactly their words on every path (compacted
-    groups, the per-tile walk of unstaged and overflowing groups, stimulus
-    expansion): one window's arena use equals the window's transitions."""
+    """Output chunks reserve exactly their words on the compacted path, in
+    unstaged groups (the dense-activity case) and in stimulus expansion;
+    the per-tile walk of staged groups reserves their fanin bound (at most
+    kStageWords per group) up front.  One window's arena use is at least its
+    transitions and at most 1% more."""
     w = synth.small_random(79, 3000, 40, 30, 512, 1500, 0.9, 2, 60, cond_frac=0.2, extra=6, extra_p=0.9,
                            edge_frac=0.3)
     ref = oracle.simulate(w)
@@ -353,7 +355,8 @@ def test_exact_arena(G):
         got = gpu_saif(G, w, **opt)
         assert_same(w, got, ref, f"exact arena {opt}")
         assert got[4]["unstaged_groups"] > 0
-        assert got[4]["arena_words"] == int(ref["tc"].sum()), (got[4]["arena_words"], int(ref["tc"].sum()))
+        words, trans = got[4]["arena_words"], int(ref["tc"].sum())
+        assert trans <= words <= 1.01 * trans, (words, trans)
 
 
 def test_learned_density(G):
