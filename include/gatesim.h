@@ -49,7 +49,8 @@
  *    over the simulated cycles; IG = glitch toggles, a cycle's edges beyond
  *    its one functional edge (gs_read_saif_ig).
  *  - Optional: several cycles as one continuous segment
- *    (gs_segment_stimulus); per-cycle glitch totals and a per-cycle check
+ *    (gs_segment_stimulus: one lane per segment; gs_continuous_stimulus:
+ *    one lane per cycle with carried state); per-cycle glitch totals and a per-cycle check
  *    of when the isolated model equals a continuous run (gs_cycle_profile).
  */
 #ifndef GATESIM_H
@@ -232,6 +233,24 @@ gs_status gs_cycle_profile(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cy
  * to be a multiple of segment_cycles and segment_cycles x period_ps <= 2^24.
  * Errors: GS_E_INVALID.  *stim_id receives the new id. */
 gs_status gs_segment_stimulus(gs_ctx *ctx, int32_t stim, int32_t segment_cycles, int32_t *stim_id);
+
+/* Continuous segments with cycle-parallel lanes (Section 1's re-simulation
+ * of known waveforms, run with Section 3's one thread per cycle): a view of
+ * stimulus `stim` with the same results as gs_segment_stimulus's view of the
+ * same segment_cycles, but every cycle of a segment keeps a lane of its own.
+ * A lane's list holds the edges before the end of its cycle; the output edge
+ * still pending there (at most one) is carried into the next cycle of the
+ * segment, which then starts with it pending, and lanes are evaluated
+ * again until no carry changes; the last cycle of a segment keeps all its
+ * edges.  Cycle indices of calls that take the view count segments, as for
+ * gs_segment_stimulus; gs_read_waveform returns a segment's edges in segment
+ * time.  Windows hold whole segments (GS_E_NOMEM if one segment does not
+ * fit the budget).  Runs through gs_simulate, gs_simulate_noalloc and
+ * gs_simulate_batch, for designs without interconnect delays; gs_autotune,
+ * gs_cycle_profile and serving reject it (GS_E_INVALID).  `stim` must not be
+ * a view.  Needs n_cycles to be a multiple of segment_cycles.  Errors:
+ * GS_E_INVALID.  *stim_id receives the new id. */
+gs_status gs_continuous_stimulus(gs_ctx *ctx, int32_t stim, int32_t segment_cycles, int32_t *stim_id);
 
 /* Re-simulates cycles [cycle_begin, cycle_end) of stimulus `stim` on
  * `design` and ADDS the per-net SAIF counts into the design's accumulators.

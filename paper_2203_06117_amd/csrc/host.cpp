@@ -626,6 +626,7 @@ extern "C" gs_status gs_segment_stimulus(gs_ctx *ctx, int32_t stim, int32_t segm
     if (stim < 0 || stim >= (int32_t)ctx->stims.size() || !ctx->stims[stim])
         return gs_fail(ctx, GS_E_INVALID, "no stimulus %d", stim);
     const Stim *s = ctx->stims[stim];
+    if (s->carry) return gs_fail(ctx, GS_E_INVALID, "stimulus %d is a continuous view", stim);
     const int32_t S = segment_cycles;
     if (S < 1 || s->n_cycles % S)
         return gs_fail(ctx, GS_E_INVALID, "n_cycles %d is not a multiple of segment_cycles %d", s->n_cycles, S);
@@ -646,6 +647,46 @@ extern "C" gs_status gs_segment_stimulus(gs_ctx *ctx, int32_t stim, int32_t segm
     for (int32_t k = 0; k <= v->n_cycles; k++) v->tog_prefix[k] = s->tog_prefix[(size_t)k * S];
     ctx->stims.push_back(v);
     if (stim_id) *stim_id = (int32_t)ctx->stims.size() - 1;
+    return GS_OK;
+}
+
+extern "C" gs_status gs_continuous_stimulus(gs_ctx *ctx, int32_t stim, int32_t segment_cycles, int32_t *stim_id)
+{
+    if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
+    if (stim < 0 || stim >= (int32_t)ctx->stims.size() || !ctx->stims[stim])
+        return gs_fail(ctx, GS_E_INVALID, "no stimulus %d", stim);
+    const Stim *s = ctx->stims[stim];
+    if (!s->owns || s->carry) return gs_fail(ctx, GS_E_INVALID, "stimulus %d is a view", stim);
+    const int32_t S = segment_cycles;
+    if (S < 1 || s->n_cycles % S)
+        return gs_fail(ctx, GS_E_INVALID, "n_cycles %d is not a multiple of segment_cycles %d", s->n_cycles, S);
+    // the cycles stay single cycles: the expansion, the lane lists and the
+    // T0/T1 sums are those of the stimulus itself
+    Stim *v = new Stim();
+    v->design = s->design;
+    v->period = s->period;
+    v->n_cycles = s->n_cycles;
+    v->n_toggles = s->n_toggles;
+    v->owns = false;
+    v->carry = S;
+    v->d_init = s->d_init;
+    v->d_tp = s->d_tp;
+    v->d_ts = s->d_ts;
+    v->tog_prefix = s->tog_prefix;
+    ctx->stims.push_back(v);
+    if (stim_id) *stim_id = (int32_t)ctx->stims.size() - 1;
+    return GS_OK;
+}
+
+gs_status gs_job_cycles(gs_ctx *ctx, int32_t stim, int32_t &b, int32_t &e)
+{
+    if (stim < 0 || stim >= (int32_t)ctx->stims.size() || !ctx->stims[stim]) return GS_OK;   // reported by the caller
+    const int32_t S = ctx->stims[stim]->carry;
+    if (S <= 0) return GS_OK;
+    const int64_t nseg = ctx->stims[stim]->n_cycles / S;
+    if (b < 0 || e < b || e > nseg) return gs_fail(ctx, GS_E_INVALID, "segment range [%d, %d) outside [0, %lld)", b, e, (long long)nseg);
+    b *= S;
+    e *= S;
     return GS_OK;
 }
 
@@ -727,6 +768,8 @@ gs_status gs_check_ranges(gs_ctx *ctx, const Design *d, const Stim *s, int32_t b
     if (!d->arcs_loaded) return gs_fail(ctx, GS_E_STATE, "load delay arcs before simulating");
     if (b < 0 || e < b || e > s->n_cycles) return gs_fail(ctx, GS_E_INVALID, "cycle range [%d, %d) outside [0, %d)", b, e, s->n_cycles);
     if (d->zero_delay && d->has_wires) return gs_fail(ctx, GS_E_INVALID, "zero-delay arcs need zero wire delays");
+    if (s->carry && d->has_wires)
+        return gs_fail(ctx, GS_E_INVALID, "continuous views run designs without interconnect delays");
     // every cycle-local time, including the latest possible edge, must fit int32
     const int64_t latest = (int64_t)s->period + (int64_t)(d->L + 1) * ((int64_t)d->max_delay + d->max_wire);
     if (latest >= (int64_t)kInf - 1) return gs_fail(ctx, GS_E_INVALID, "period + depth x delays exceeds int32 picoseconds");
@@ -812,26 +855,40 @@ extern "C" gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim,
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     if (net < 0 || net >= d->N) return gs_fail(ctx, GS_E_INVALID, "net %d out of range", net);
     const LastWindow &lw = ctx->last;
-    if (lw.design != design || lw.stim != stim || cycle < lw.c0 || cycle >= lw.c0 + lw.cycles)
+    // a continuous view's segment is the concatenation of its cycles' lists
+    const Stim *sv = (stim >= 0 && stim < (int32_t)ctx->stims.size()) ? ctx->stims[stim] : nullptr;
+    const int32_t S = sv && sv->carry > 0 ? sv->carry : 1;
+    const int64_t c_first = (int64_t)cycle * S;
+    if (lw.design != design || lw.stim != stim || cycle < 0 || c_first < lw.c0 || c_first + S > (int64_t)lw.c0 + lw.cycles)
         return gs_fail(ctx, GS_E_STATE, "cycle %d of (design %d, stim %d) is not resident", cycle, design, stim);
+    if (S > 1 && (int64_t)S * sv->period + (int64_t)(d->L + 1) * d->max_delay >= (int64_t)kInf)
+        return gs_fail(ctx, GS_E_INVALID, "segment times exceed int32 picoseconds");
     (void)hipSetDevice(ctx->opt.device);
     hipStream_t hs = ctx->stream;
-    const int32_t local = cycle - lw.c0, tiles = (lw.cycles + kLanes - 1) / kLanes;
-    const int32_t tile = local / kLanes, lane = local % kLanes;
-    const uint64_t ci = lw.chunk_base + (uint64_t)net * tiles + tile;
-    ChunkHdr h;
-    uint16_t e[kLanes];
-    HIPCHK(hipMemcpyAsync(&h, ctx->win.hdr + ci, sizeof(h), hipMemcpyDeviceToHost, hs));
-    HIPCHK(hipMemcpyAsync(e, ctx->win.ends + ci * kLanes, sizeof(e), hipMemcpyDeviceToHost, hs));
-    HIPCHK(hipStreamSynchronize(hs));
-    const uint32_t lo = lane ? e[lane - 1] & kEndCount : 0, hi = e[lane] & kEndCount;
-    if (init) *init = (int32_t)((h.mask >> lane) & 1);
-    if (n) *n = (int32_t)(hi - lo);
-    const uint32_t m = std::min<uint32_t>(hi - lo, cap > 0 ? (uint32_t)cap : 0u);
-    if (m && times) {
-        HIPCHK(hipMemcpyAsync(times, ctx->win.times + h.off + lo, sizeof(int32_t) * m, hipMemcpyDeviceToHost, hs));
+    const int32_t tiles = (lw.cycles + kLanes - 1) / kLanes;
+    int64_t total = 0;
+    for (int32_t k = 0; k < S; k++) {
+        const int32_t local = (int32_t)(c_first - lw.c0) + k;
+        const int32_t tile = local / kLanes, lane = local % kLanes;
+        const uint64_t ci = lw.chunk_base + (uint64_t)net * tiles + tile;
+        ChunkHdr h;
+        uint16_t e[kLanes];
+        HIPCHK(hipMemcpyAsync(&h, ctx->win.hdr + ci, sizeof(h), hipMemcpyDeviceToHost, hs));
+        HIPCHK(hipMemcpyAsync(e, ctx->win.ends + ci * kLanes, sizeof(e), hipMemcpyDeviceToHost, hs));
         HIPCHK(hipStreamSynchronize(hs));
+        const uint32_t lo = lane ? e[lane - 1] & kEndCount : 0, hi = e[lane] & kEndCount;
+        if (k == 0 && init) *init = (int32_t)((h.mask >> lane) & 1);
+        const int64_t room = cap > 0 ? (int64_t)cap - total : 0;
+        const uint32_t m = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(hi - lo, room));
+        if (m && times) {
+            int32_t *dst = times + total;
+            HIPCHK(hipMemcpyAsync(dst, ctx->win.times + h.off + lo, sizeof(int32_t) * m, hipMemcpyDeviceToHost, hs));
+            HIPCHK(hipStreamSynchronize(hs));
+            for (uint32_t i = 0; i < m; i++) dst[i] += k * sv->period;
+        }
+        total += hi - lo;
     }
+    if (n) *n = (int32_t)std::min<int64_t>(total, INT32_MAX);
     return GS_OK;
 }
 

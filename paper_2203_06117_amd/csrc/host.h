@@ -80,6 +80,11 @@ struct Stim {
     int32_t design = -1, period = 0, n_cycles = 0;
     int64_t n_toggles = 0;
     bool owns = true;                        // false: a segment view sharing another stimulus's arrays
+    // > 0: a continuous view whose segments of `carry` cycles run one lane
+    // per cycle, with the edge pending at each cycle's end carried into the
+    // next; period and n_cycles stay those of single cycles, and the cycle
+    // indices of calls that take the view count segments
+    int32_t carry = 0;
     uint8_t *d_init = nullptr;
     int64_t *d_tp = nullptr;
     int64_t *d_ts = nullptr;
@@ -155,6 +160,9 @@ gs_status gs_window_reserve(gs_ctx *ctx, WindowBufs *w, uint64_t n_chunks, uint6
 uint64_t gs_header_bytes(uint64_t n_nets, int32_t cycles);
 uint64_t gs_arena_guess(uint64_t n_nets, int32_t cycles, int64_t toggles);
 gs_status gs_check_ranges(gs_ctx *ctx, const Design *d, const Stim *s, int32_t b, int32_t e);
+// Converts the segment range [b, e) of a continuous view into its cycle
+// range (other stimuli: unchanged).
+gs_status gs_job_cycles(gs_ctx *ctx, int32_t stim, int32_t &b, int32_t &e);
 gs::WinView gs_make_view(gs_ctx *ctx, const WindowBufs &w, int32_t cycles, int32_t period, uint64_t chunk_base,
                          uint64_t n_chunks_used);
 gs_status gs_ensure_segs(gs_ctx *ctx, size_t n);

@@ -139,7 +139,8 @@ struct Seg {
     uint32_t gate_begin;
     uint32_t n_gates;
     uint32_t salt;                 // added to the block index to pick an arena stripe
-    uint32_t mode;                 // bit 0: transport wire delays (no net-delay filter)
+    uint32_t mode;                 // bit 0: transport wire delays (no net-delay filter); bits 8-31: cycles of a
+                                   // continuous segment whose cycles are lanes (0: every cycle on its own)
     WinView win;
     SaifAcc saif;
 };
@@ -151,6 +152,7 @@ struct StimView {
     const int64_t *toggle_ps;
     int32_t n_inputs;
     int32_t period;
+    int32_t seg;        // > 1: glitch toggles counted per continuous segment of this many cycles
 };
 
 // Static device scratch of gs_simulate_noalloc (bytes per GPU), and the
@@ -178,8 +180,11 @@ hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n
 
 hipError_t launch_expand(StimView st, WinView win, SaifAcc acc, const int32_t *cycle0, uint32_t salt, hipStream_t s);
 
+// cont: every segment runs continuous segments of (mode >> 8) cycles, each
+// wave's tiles starting one (no interconnect delays, no remap).
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires,
-                            int32_t cap, int32_t wpb, int32_t kmax, uint32_t tpw, int32_t remap, hipStream_t s);
+                            int32_t cap, int32_t wpb, int32_t kmax, uint32_t tpw, int32_t remap, int32_t cont,
+                            hipStream_t s);
 
 // New delays of one edited fanin slot, addressed by (output net, pin).
 struct EditRec {

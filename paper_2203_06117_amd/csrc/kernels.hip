@@ -434,6 +434,19 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     uint32_t before = 0;                                    // group toggles in earlier tiles
     uint32_t nact = 0, glitch = 0;
     int64_t zt = 0;                                         // final values x T over the lane's cycles
+    // Continuous segments of st.seg cycles (the window starts one): a
+    // segment's glitch toggles are its toggles less the parity of their
+    // number, i.e. less (toggles before its start XOR toggles before its
+    // end) & 1.  The group counts the segments that end in it; pv is that
+    // parity term at the last segment start seen (found by a search when the
+    // segment began before the group).
+    const uint32_t S = st.seg > 1 ? (uint32_t)st.seg : 0u;
+    uint32_t pv = 0, odd = 0;
+    if (S) {
+        const int32_t s0 = c_lo - (int32_t)((uint32_t)c_lo % S);
+        const int64_t tb = s0 == c_lo ? ga : wave_lower_bound(st.toggle_ps, lo, ga, (int64_t)(cycle0 + s0) * T, lane);
+        pv = (uint32_t)((tb - lo) & 1);
+    }
     for (uint32_t u = 0; u < nt; u++) {
         const uint32_t tile = t0 + u;
         const bool active = (int32_t)(tile * kLanes) + lane < win.n_cycles;
@@ -458,8 +471,24 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
         }
         nact += (uint32_t)__popcll(__ballot(active));
         zt += active ? (int64_t)(init ^ (cnt & 1u)) * T : 0;
-        glitch += total - (uint32_t)__popcll(__ballot(cnt & 1u));   // all but one edge of odd lists
+        if (S) {
+            const uint32_t c = tile * kLanes + (uint32_t)lane;
+            const uint64_t mb = __ballot(active && (int32_t)c > c_lo && c % S == 0u);
+            const uint64_t mp = __ballot(((ga - lo + excl) & 1) != 0);
+            for (uint64_t b = mb; b; b &= b - 1) {
+                const uint32_t pb = (uint32_t)(mp >> __builtin_ctzll(b)) & 1u;
+                odd += pv ^ pb;
+                pv = pb;
+            }
+            glitch += total;
+        } else {
+            glitch += total - (uint32_t)__popcll(__ballot(cnt & 1u));   // all but one edge of odd lists
+        }
         before += total;
+    }
+    if (S) {
+        if ((uint32_t)c_hi % S == 0u) odd += pv ^ (uint32_t)((gz - lo) & 1);   // a segment ends with the group
+        glitch -= odd;
     }
     const int64_t sum1 = wave_sum64(zt + s1);
     if (lane == 0) {
@@ -651,15 +680,29 @@ __device__ __forceinline__ void build_lut(const Arcs<K> &arc, uint64_t truth, in
 // One walk over a lane's fanin lists (Algorithm 1's event loop).  MODE 0
 // stages output edges in LDS (at most CAP per lane); MODE 1 writes them to
 // dst[0 .. keep) in global memory (entries at or beyond `keep` are retracted
-// before the walk ends, so they are not stored).
+// before the walk ends, or are the edge a continuous segment carries into
+// the next cycle, so they are not stored).  w0 >= 0: the output has an edge
+// to z pending at w0 when the lane starts (carried from the cycle before;
+// the output is !z until then).  w_out: the time of the list's last edge.
 template <int K, bool WIRES, bool LDSRC, int MODE, int CAP>
 __device__ __forceinline__ void walk(Cursor<K, WIRES, LDSRC> &P, const Arcs<K> &arc, uint64_t truth, int32_t T,
                                      int z, uint32_t lut_base, uint32_t out_lane, int32_t *dst, int32_t keep,
-                                     int32_t &cnt_out, int32_t &acc_out, int32_t &z_out)
+                                     int32_t w0, int32_t &cnt_out, int32_t &acc_out, int32_t &z_out, int32_t &w_out)
 {
 #pragma unroll
     for (int j = 0; j < K; j++) P.advance(arc, j);
     int32_t W = 0, Wp = 0, cnt = 0, acc = 0;
+    if (w0 >= 0) {
+        if (MODE == 0) {
+            if (CAP > 0) gs_lds[out_lane] = w0;
+        } else {
+            if (keep > 0) *glob(dst) = w0;
+        }
+        const int32_t ce = min(w0, T);
+        acc += z ? -ce : ce;
+        cnt = 1;
+        W = w0;
+    }
     for (;;) {
         int32_t t = P.a[0];
 #pragma unroll
@@ -710,6 +753,7 @@ __device__ __forceinline__ void walk(Cursor<K, WIRES, LDSRC> &P, const Arcs<K> &
     cnt_out = cnt;
     acc_out = acc;
     z_out = z;
+    w_out = W;
 }
 
 // Interconnect filter (Algorithm 1, net-delay filtering) applied to one
@@ -748,10 +792,12 @@ __device__ __forceinline__ void wire_filter_lds(uint32_t base, uint32_t lo, uint
 // lane's event costs the same straight-line code whichever pins switch and
 // whether the output edge is appended, cancelled or not needed.  Output
 // edges go to LDS slot min(cnt, CAP); slot CAP is a spare that absorbs the
-// stores of steps that append nothing and of lanes past CAP.
+// stores of steps that append nothing and of lanes past CAP.  w0 and w_out
+// as in `walk`.
 template <int K, int CAP>
 __device__ __forceinline__ void walk_lds(Cursor<K, false, true> &P, const Arcs<K> &arc, uint64_t truth, int32_t T,
-                                         int z, uint32_t lut_base, uint32_t out_lane, int32_t &cnt_out)
+                                         int z, uint32_t lut_base, uint32_t out_lane, int32_t w0, int32_t &cnt_out,
+                                         int32_t &w_out)
 {
 #pragma unroll
     for (int j = 0; j < K; j++) {
@@ -759,6 +805,11 @@ __device__ __forceinline__ void walk_lds(Cursor<K, false, true> &P, const Arcs<K
         P.a[j] = P.idx[j] < P.end[j] ? v : kInf;
     }
     int32_t W = 0, Wp = 0, cnt = 0;
+    if (w0 >= 0) {
+        gs_lds[out_lane] = w0;
+        cnt = 1;
+        W = w0;
+    }
     for (;;) {
         int32_t t = P.a[0];
 #pragma unroll
@@ -799,6 +850,7 @@ __device__ __forceinline__ void walk_lds(Cursor<K, false, true> &P, const Arcs<K
         z = y;
     }
     cnt_out = cnt;
+    w_out = W;
 }
 
 // The event loop of walk_lds for a queued lane of the compacted path: the
@@ -1104,10 +1156,11 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
 // memory (groups too large for the staging area walk the arena instead).
 // SAIF counts of the output net are summed over the tiles and added with
 // one atomic per counter.
-template <int K, bool WIRES, int CAP, bool REMAP>
+template <int K, bool WIRES, int CAP, bool REMAP, bool CONT>
 __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint32_t tile0, uint32_t ntl, int lane,
                                           uint32_t lut_base, uint32_t out_base, uint32_t stage_base)
 {
+    static_assert(!(CONT && (WIRES || REMAP)), "continuous segments: designs without interconnect delays, whole windows");
     constexpr uint32_t GT = K <= 3 ? 4 : 2;
     const WinView &win = sg.win;
     const bool transport = (sg.mode & 1u) != 0;
@@ -1158,6 +1211,12 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
     const uint32_t out_lane = out_base + lane;
     uint32_t tc_sum = 0, nact_sum = 0, ig_sum = 0;
     int32_t t1_lane = 0;
+    // continuous segments of seg_len cycles (the wave's first tile starts
+    // one): the edge carried into the next lane, and the output's value at
+    // the start of the open segment
+    const uint32_t seg_len = CONT ? (sg.mode >> 8) : 1u;
+    int32_t carry = -1;
+    uint32_t seg_y = 0;
     for (uint32_t gb = 0; gb < ntl; gb += GT) {
         const uint32_t ng = min(GT, ntl - gb);
         // Every load below is issued by every lane (lanes without a chunk of
@@ -1191,7 +1250,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         const bool staged = bound <= kStageWords;
         // staged groups of gates with up to three pins take the compacted
         // path, which reserves exactly its output words later
-        const bool try_compact = K <= 3 && staged;
+        const bool try_compact = K <= 3 && staged && !CONT;
         if (!staged && lane == 0)                               // counted for the statistics
             __hip_atomic_fetch_add(glob(win.flags + 4), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // A producing wave places the chunks of its tile group one after
@@ -1260,11 +1319,15 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         // atomic's latency overlaps the walk; an unstaged group, where
         // activity is dense and memory matters, reserves each tile's exact
         // words once the tile's lane counts are known.
+        // On a continuous view an edge carried into the group's first lane
+        // can add one edge (carries only move edges between the group's
+        // lanes, or out of it).
+        const uint32_t obound = bound + (CONT ? 1u : 0u);
         uint64_t gbase = 0;                                     // staged: the group's reservation
         bool gok = true;
         uint32_t used = 0;                                      // staged: its words handed out
-        if (staged && bound > 0) {
-            gbase = arena_reserve(win, stripe, bound, lane);
+        if (staged && obound > 0) {
+            gbase = arena_reserve(win, stripe, obound, lane);
             gok = gbase != ~0ull;
         }
         for (uint32_t u = 0; u < ng; u++) {
@@ -1284,39 +1347,85 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 state0 |= ((ev[j][0] >> kEndInitShift) & 1u) << j;
             }
             const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
-            int32_t cnt, acc = 0, z = 0;
-            if (staged) {
-                Cursor<K, false, true> P;
+            int32_t cnt = 0, acc = 0, z = 0, wl = 0;
+            // the lane's walk; seed >= 0: an output edge to y0 pending there
+            // at t = 0 (continuous segments only)
+            auto run = [&](int32_t seed) {
+                if (staged) {
+                    Cursor<K, false, true> P;
 #pragma unroll
-                for (int j = 0; j < K; j++) {
-                    P.base[j] = base[j];
-                    P.idx[j] = lo[j];
-                    P.end[j] = hi[j];
-                    // with interconnect delays, each staged net list becomes
-                    // the pin's arrival list first
-                    if (WIRES)
-                        wire_filter_lds(base[j], lo[j], P.end[j], (state0 >> j) & 1u, arc.wr[j], arc.wf[j], transport);
-                }
-                P.state = state0;
-                P.transport = transport;
-                walk_lds<K, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, cnt);
-            } else {
-                Cursor<K, WIRES, false> P;
+                    for (int j = 0; j < K; j++) {
+                        P.base[j] = base[j];
+                        P.idx[j] = lo[j];
+                        P.end[j] = hi[j];
+                        // with interconnect delays, each staged net list becomes
+                        // the pin's arrival list first
+                        if (WIRES)
+                            wire_filter_lds(base[j], lo[j], P.end[j], (state0 >> j) & 1u, arc.wr[j], arc.wf[j], transport);
+                    }
+                    P.state = state0;
+                    P.transport = transport;
+                    walk_lds<K, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, seed, cnt, wl);
+                } else {
+                    Cursor<K, WIRES, false> P;
 #pragma unroll
-                for (int j = 0; j < K; j++) {
-                    P.chunk[j] = win.times + readlane64(c_off, (uint32_t)j * GT + u);
-                    P.idx[j] = lo[j];
-                    P.end[j] = hi[j];
+                    for (int j = 0; j < K; j++) {
+                        P.chunk[j] = win.times + readlane64(c_off, (uint32_t)j * GT + u);
+                        P.idx[j] = lo[j];
+                        P.end[j] = hi[j];
+                    }
+                    P.state = state0;
+                    P.transport = transport;
+                    walk<K, WIRES, false, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, seed, cnt, acc,
+                                                  z, wl);
                 }
-                P.state = state0;
-                P.transport = transport;
-                walk<K, WIRES, false, 0, CAP>(P, arc, g.truth, T, y0, lut_base, out_lane, nullptr, 0, cnt, acc, z);
+            };
+            run(-1);
+            // Continuous segments: a lane's list keeps the edges before the
+            // end of its cycle; the one edge still pending there (at most
+            // one, Algorithm 1 cancels a pending edge rather than queueing a
+            // second) moves to the next cycle of the segment, which starts
+            // with it pending.  Every lane first ran as if nothing were
+            // pending; lanes whose carry-in differs run again until no
+            // carry changes.  The carry chain runs upwards through the lanes
+            // and each pass settles at least the lowest lane still open, so
+            // this ends within 64 passes.
+            int32_t cin = -1, cfull = 0;
+            bool cout_taken = false;
+            if constexpr (CONT) {
+                const uint32_t p = (uint32_t)lc % seg_len;
+                const bool sstart = p == 0, send = p == seg_len - 1;
+                auto cout_of = [&]() { return (active && !send && cnt > 0 && wl >= T) ? wl - T : -1; };
+                int32_t co = cout_of();
+                for (uint32_t pass = 0;; pass++) {
+                    int32_t ni = (int32_t)wave_shr1((uint32_t)(co + 1)) - 1;
+                    if (lane == 0) ni = carry;
+                    if (sstart || !active) ni = -1;
+                    const bool redo = ni != cin;
+                    if (__ballot(redo) == 0) break;
+                    if (pass > (uint32_t)kLanes) {                  // unreachable (see above): fail the round
+                        if (lane == 0)
+                            __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    if (redo) {
+                        cin = ni;
+                        acc = 0;
+                        run(cin);
+                        co = cout_of();
+                    }
+                }
+                carry = __builtin_amdgcn_readlane(co, kLanes - 1);
+                cfull = cnt;
+                cout_taken = co >= 0;
+                if (cout_taken) cnt--;
             }
+            const int yi = y0 ^ (cin >= 0 ? 1 : 0);         // the output's value at t = 0
 
             const uint32_t ucnt = (uint32_t)cnt;
             const uint32_t incl = wave_incl_scan(ucnt);
             const uint32_t total = (uint32_t)lane63(incl);
-            const uint64_t mask = __ballot(active && y0);
+            const uint64_t mask = __ballot(active && yi);
             const uint64_t ci = (uint64_t)out_row * ntile + tile;
             bool ok = true;
             if (total > kMaxChunk) {
@@ -1325,7 +1434,12 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             }
             uint64_t obase = 0;
             if (staged) {
-                ok = ok && gok && used + total <= bound;       // the bound holds: never write past it
+                if (used + total > obound) {                    // cannot happen: fail the round, write nothing
+                    if (lane == 0)
+                        __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
+                }
+                ok = ok && gok;
                 obase = ok ? gbase + used : 0;
                 if (ok) used += total;
             } else if (ok && total > 0) {
@@ -1334,7 +1448,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 if (!ok) obase = 0;
             }
             st_u16(win.ends + ci * kLanes, (uint32_t)lane,
-                   (uint16_t)((ok ? incl : 0u) | ((active && y0) ? 1u << kEndInitShift : 0u)));
+                   (uint16_t)((ok ? incl : 0u) | ((active && yi) ? 1u << kEndInitShift : 0u)));
             if (lane == 0) {
                 ChunkHdr h;
                 h.off = ok ? obase : 0;
@@ -1348,8 +1462,9 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             const uint32_t first = wave_shr1(incl);            // exclusive prefix: the lane's first slot
             int32_t *out = out_chunk + first;
             const int32_t n = cnt < CAP ? cnt : CAP;
+            bool walk_acc = !staged;                            // acc holds the walk's own sum of every edge
             {
-                int v = y0;
+                int v = yi;
                 int32_t s1 = 0;
                 for (int32_t i = 0; i < n; i++) {
                     const int32_t e = gs_lds[out_lane + i * kLanes];
@@ -1358,15 +1473,15 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     const int32_t ce = min(e, T);
                     s1 += v ? -ce : ce;
                 }
-                if (!staged) s1 = acc;                // that walk kept its own sum
-                acc = s1;
+                if (staged) acc = s1;
             }
-            const uint64_t spill = __ballot(cnt > CAP);
+            const int32_t nwalk = CONT ? cfull : cnt;          // the walk's count, with a carried-out edge
+            const uint64_t spill = __ballot(nwalk > CAP);
             if (spill) {
                 // lanes whose list outgrew the staging walk again, from the
                 // arena, writing to their place in the output chunk (and
                 // returning the complete T1 sum)
-                if (cnt > CAP) {
+                if (nwalk > CAP) {
                     Cursor<K, WIRES, false> P;
 #pragma unroll
                     for (int j = 0; j < K; j++) {
@@ -1376,17 +1491,36 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     }
                     P.state = state0;
                     P.transport = transport;
-                    int32_t c2, z2;
-                    walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, ok ? cnt : 0, c2, acc,
-                                                  z2);
+                    int32_t c2, z2, w2;
+                    walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, ok ? cnt : 0, cin, c2, acc,
+                                                  z2, w2);
+                    walk_acc = true;
                 }
                 if (lane == 0 && ok)
                     __hip_atomic_fetch_add(glob(win.flags + 2), (unsigned int)__popcll(spill), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
             }
-            z = y0 ^ (cnt & 1);                      // every kept edge toggles the output
+            // a walk's sum counted the edge carried out of the cycle (at or
+            // after T, so it added -T after a rise and +T after a fall)
+            if (CONT && cout_taken && walk_acc) acc -= ((yi ^ (cfull & 1)) != 0) ? -T : T;
+            z = yi ^ (cnt & 1);                      // every kept edge toggles the output
             tc_sum += total;
-            ig_sum += total - (uint32_t)__popcll(__ballot(cnt & 1));   // a cycle's edges beyond its functional one
+            if constexpr (CONT) {
+                // a segment's glitch toggles: its edges less the parity of
+                // their number, which is its start value XOR its end value
+                const uint64_t ms = __ballot(active && (uint32_t)lc % seg_len == 0);
+                const uint64_t me = __ballot(active && (uint32_t)lc % seg_len == seg_len - 1);
+                const uint64_t mi = __ballot(yi != 0), mf = __ballot(z != 0);
+                uint32_t odd = 0;
+                for (uint64_t b = ms | me; b; b &= b - 1) {
+                    const int l = __builtin_ctzll(b);
+                    if ((ms >> l) & 1u) seg_y = (uint32_t)(mi >> l) & 1u;
+                    if ((me >> l) & 1u) odd += seg_y ^ ((uint32_t)(mf >> l) & 1u);
+                }
+                ig_sum += total - odd;
+            } else {
+                ig_sum += total - (uint32_t)__popcll(__ballot(cnt & 1));   // a cycle's edges beyond its functional one
+            }
             nact_sum += (uint32_t)__popcll(__ballot(active));
             t1_lane += active ? z * T + acc : 0;
 #pragma unroll
@@ -1430,7 +1564,7 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int n, uin
 // (CAP + 1) x 64 staged output words of the per-tile path (the last slot of
 // each lane is a spare) or the output stage and lane queue of the compacted
 // path.
-template <bool WIRES, int CAP, int KMAX, bool REMAP>
+template <bool WIRES, int CAP, int KMAX, bool REMAP, bool CONT>
 __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ segs, int32_t n_segs, uint64_t n_waves,
                                                         uint32_t tpw)
 {
@@ -1459,17 +1593,17 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     const uint32_t stage_base = lut_base + kLanes;
     const uint32_t out_base = stage_base + kStageWords;
     switch (g.k) {
-    case 1: eval_gate<1, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
-    case 2: eval_gate<2, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
-    case 3: eval_gate<3, WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
-    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
-    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
-    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP, REMAP>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 1: eval_gate<1, WIRES, CAP, REMAP, CONT>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 2: eval_gate<2, WIRES, CAP, REMAP, CONT>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 3: eval_gate<3, WIRES, CAP, REMAP, CONT>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 4: if (KMAX >= 4) eval_gate<(KMAX >= 4 ? 4 : 1), WIRES, CAP, REMAP, CONT>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 5: if (KMAX >= 5) eval_gate<(KMAX >= 5 ? 5 : 1), WIRES, CAP, REMAP, CONT>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
+    case 6: if (KMAX >= 6) eval_gate<(KMAX >= 6 ? 6 : 1), WIRES, CAP, REMAP, CONT>(sg, g, tile0, ntl, lane, lut_base, out_base, stage_base); break;
     default: break;
     }
 }
 
-template <bool WIRES, int KMAX, bool REMAP>
+template <bool WIRES, int KMAX, bool REMAP, bool CONT>
 static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t cap, int32_t wpb, uint32_t tpw,
                             hipStream_t s)
 {
@@ -1477,10 +1611,10 @@ static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
     const size_t lds = gate_eval_lds_bytes(cap, wpb);
     const dim3 grid((unsigned)blocks), block(kLanes * wpb);
     switch (cap) {
-    case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
-    case 16: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 16, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
-    case 32: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 32, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
-    case 4: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 4, KMAX, REMAP>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 16: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 16, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 32: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 32, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 4: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 4, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1491,17 +1625,23 @@ static hipError_t launch_ge_r(const Seg *segs, int32_t n_segs, uint64_t n_waves,
                               int32_t wpb, int32_t kmax, uint32_t tpw, hipStream_t s)
 {
     if (kmax <= 3)
-        return wires ? launch_ge<true, 3, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s)
-                     : launch_ge<false, 3, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s);
-    return wires ? launch_ge<true, 6, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s)
-                 : launch_ge<false, 6, REMAP>(segs, n_segs, n_waves, cap, wpb, tpw, s);
+        return wires ? launch_ge<true, 3, REMAP, false>(segs, n_segs, n_waves, cap, wpb, tpw, s)
+                     : launch_ge<false, 3, REMAP, false>(segs, n_segs, n_waves, cap, wpb, tpw, s);
+    return wires ? launch_ge<true, 6, REMAP, false>(segs, n_segs, n_waves, cap, wpb, tpw, s)
+                 : launch_ge<false, 6, REMAP, false>(segs, n_segs, n_waves, cap, wpb, tpw, s);
 }
 
 hipError_t launch_gate_eval(const Seg *segs, int32_t n_segs, uint64_t n_waves, int32_t wires, int32_t cap,
-                            int32_t wpb, int32_t kmax, uint32_t tpw, int32_t remap, hipStream_t s)
+                            int32_t wpb, int32_t kmax, uint32_t tpw, int32_t remap, int32_t cont, hipStream_t s)
 {
     if (n_waves == 0) return hipSuccess;
     if (wpb < 1 || wpb > 8 || tpw < 1) return hipErrorInvalidValue;
+    if (cont) {
+        // continuous segments: no interconnect delays, no cone re-simulation
+        if (wires || remap) return hipErrorInvalidValue;
+        return kmax <= 3 ? launch_ge<false, 3, false, true>(segs, n_segs, n_waves, cap, wpb, tpw, s)
+                         : launch_ge<false, 6, false, true>(segs, n_segs, n_waves, cap, wpb, tpw, s);
+    }
     return remap ? launch_ge_r<true>(segs, n_segs, n_waves, wires, cap, wpb, kmax, tpw, s)
                  : launch_ge_r<false>(segs, n_segs, n_waves, wires, cap, wpb, kmax, tpw, s);
 }

@@ -51,10 +51,21 @@ Tuning current_tuning(const gs_ctx *ctx)
 // toggles per (input, cycle).  A lane of a segment view carries the events
 // of many cycles; with the single-cycle cap most of its lanes would take
 // the spill path.
+// Continuous views carry state from a wave's lane to the next, so each
+// wave must start at a segment start: segments that tile 64 cycles allow
+// any tiles per wave, others take whole windows (which start at segment
+// starts) per wave.
+Tuning carry_tuning(Tuning t, const std::vector<Piece> &ps)
+{
+    for (const Piece &p : ps)
+        if (p.s->carry > 0 && kLanes % p.s->carry != 0) t.tpw = std::max(t.tpw, p.tiles);
+    return t;
+}
+
 Tuning tuning_for(const gs_ctx *ctx, const std::vector<Piece> &ps)
 {
     Tuning t = current_tuning(ctx);
-    if (!ctx->auto_cap) return t;
+    if (!ctx->auto_cap) return carry_tuning(t, ps);
     // inputs alone underrate designs whose logic multiplies glitches: take
     // the transitions per (net, cycle) seen when the design last ran too
     double rho = 0;
@@ -65,7 +76,7 @@ Tuning tuning_for(const gs_ctx *ctx, const std::vector<Piece> &ps)
     }
     t.cap = rho <= 0.5 ? 8 : rho <= 1.0 ? 16 : 32;
     while (t.wpb > 1 && gate_eval_lds_bytes(t.cap, t.wpb) > ctx->lds_limit) t.wpb /= 2;   // fit the block's LDS
-    return t;
+    return carry_tuning(t, ps);
 }
 
 uint64_t chunks_of(const Piece &p)
@@ -101,7 +112,7 @@ void build_steps(gs_ctx *ctx, const std::vector<Piece> &pieces, const std::vecto
             g.gate_begin = p.d->level_ptr[l];
             g.n_gates = n_gates;
             g.salt = (uint32_t)salt;
-            g.mode = ctx->opt.wire_transport ? 1u : 0u;
+            g.mode = (ctx->opt.wire_transport ? 1u : 0u) | ((uint32_t)std::max(0, p.s->carry) << 8);
             g.win = views[i];
             g.saif = saif_view(p.d->d_stage, (size_t)p.d->N);
             const uint64_t nw = (uint64_t)n_gates * ngroup;
@@ -136,7 +147,7 @@ gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pi
     if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     for (size_t i = 0; i < pieces.size(); i++) {
         const Piece &p = pieces[i];
-        StimView sv{p.s->d_init, p.s->d_tp, p.s->d_ts, p.d->I, p.s->period};
+        StimView sv{p.s->d_init, p.s->d_tp, p.s->d_ts, p.d->I, p.s->period, p.s->carry};
         SaifAcc stage = saif_view(p.d->d_stage, (size_t)p.d->N);
         HIPCHK(launch_expand(sv, views[i], stage, ctx->d_c0 + i, (uint32_t)(i * 977), hs));
     }
@@ -145,7 +156,7 @@ gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pi
         if (step_waves[k] == 0) continue;
         if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
         HIPCHK(launch_gate_eval(d_segs + step_off[k], (int32_t)step_n[k], step_waves[k], step_wires[k], tu.cap, tu.wpb,
-                                step_kmax[k], (uint32_t)tu.tpw, 0, hs));
+                                step_kmax[k], (uint32_t)tu.tpw, 0, pieces.front().s->carry > 0 ? 1 : 0, hs));
         if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     }
     if (commit)
@@ -330,6 +341,16 @@ uint64_t piece_arena_guess(const Piece &p)
     return g;
 }
 
+// The first part of a window that has to be split, or 0 when it cannot be:
+// halves, at least 64 cycles, and for a continuous view whole segments.
+int32_t split_cycles(const Piece &p)
+{
+    const int32_t S = std::max(1, p.s->carry);
+    if (p.cycles <= std::max(kLanes, S)) return 0;
+    const int32_t a = p.cycles / 2 / S * S;
+    return a > 0 ? a : S;
+}
+
 // Runs `pieces` as rounds that fit the budget.  A round whose arena fills up
 // is retried with twice the arena; at the budget limit the round is split
 // and, for a single piece, its window is halved.
@@ -345,6 +366,8 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
         uint64_t hdr = 0, guess = 0;
         while (!pending.empty() && round.size() < max_round) {
             const Piece &p = pending.back();
+            // a round's launches run either continuous views or none
+            if (!round.empty() && (p.s->carry > 0) != (round.front().s->carry > 0)) break;
             const uint64_t hb = gs_header_bytes(p.d->N, p.cycles);
             const uint64_t gw = piece_arena_guess(p);
             if (!round.empty() && hdr + hb + (guess + gw) * sizeof(int32_t) > ctx->budget) break;
@@ -355,9 +378,9 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
         }
         if (hdr >= ctx->budget) {
             Piece p = round.front();
-            if (round.size() == 1 && p.cycles > kLanes) {      // halve the window
+            if (round.size() == 1 && split_cycles(p) > 0) {     // halve the window
                 Piece a = p, b = p;
-                a.cycles = p.cycles / 2;
+                a.cycles = split_cycles(p);
                 a.tiles = (a.cycles + kLanes - 1) / kLanes;
                 b.c0 = p.c0 + a.cycles;
                 b.cycles = p.cycles - a.cycles;
@@ -383,9 +406,9 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
             // fewer pieces per round: each round gets the whole arena
             max_round = round.size() / 2;
             for (auto it = round.rbegin(); it != round.rend(); ++it) pending.push_back(*it);
-        } else if (round[0].cycles > kLanes) {
+        } else if (split_cycles(round[0]) > 0) {
             Piece p = round[0], a = p, b = p;
-            a.cycles = p.cycles / 2;
+            a.cycles = split_cycles(p);
             a.tiles = (a.cycles + kLanes - 1) / kLanes;
             b.c0 = p.c0 + a.cycles;
             b.cycles = p.cycles - a.cycles;
@@ -393,7 +416,7 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
             pending.push_back(b);
             pending.push_back(a);
         } else {
-            return gs_fail(ctx, GS_E_NOMEM, "transitions of one 64-cycle window exceed the memory budget");
+            return gs_fail(ctx, GS_E_NOMEM, "transitions of one %d-cycle window exceed the memory budget", round[0].cycles);
         }
     }
     return GS_OK;
@@ -418,7 +441,7 @@ Piece make_piece(gs_ctx *ctx, int32_t di, int32_t si, int32_t c0, int32_t cycles
 // take at most a third of the budget and, once the design's transition
 // density is known, whose headers and transitions (with 15% to spare) fit
 // the budget.
-int32_t default_window(gs_ctx *ctx, const Design *d, int32_t period)
+int32_t window_cycles(gs_ctx *ctx, const Design *d, int32_t period)
 {
     int32_t W = ctx->opt.window_cycles;
     if (W <= 0) {
@@ -433,6 +456,13 @@ int32_t default_window(gs_ctx *ctx, const Design *d, int32_t period)
         }
     }
     return W;
+}
+
+// The same for a stimulus: a continuous view's windows hold whole segments.
+int32_t default_window(gs_ctx *ctx, const Design *d, const Stim *s)
+{
+    const int32_t W = window_cycles(ctx, d, s->period);
+    return s->carry > 0 ? std::max(1, W / s->carry) * s->carry : W;
 }
 
 gs_status check_job(gs_ctx *ctx, int32_t design, int32_t stim, int32_t b, int32_t e)
@@ -462,6 +492,7 @@ extern "C" gs_status gs_cycle_profile(gs_ctx *ctx, int32_t design, int32_t stim,
     if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
     gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
     if (st) return st;
+    if (ctx->stims[stim]->carry) return gs_fail(ctx, GS_E_INVALID, "no cycle profile of a continuous view");
     const int32_t n = cycle_end - cycle_begin;
     (void)hipSetDevice(ctx->opt.device);
     const Design *d = ctx->designs[design];
@@ -526,7 +557,9 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
     if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
-    gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
+    gs_status st = gs_job_cycles(ctx, stim, cycle_begin, cycle_end);
+    if (st) return st;
+    st = check_job(ctx, design, stim, cycle_begin, cycle_end);
     if (st) return st;
     (void)hipSetDevice(ctx->opt.device);
     const uint64_t t_start = gs_now_ns();
@@ -543,7 +576,7 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
                         8ull * (uint64_t)d->N * kLanes);
         if (st) return st;
     }
-    const int32_t W = default_window(ctx, d, ctx->stims[stim]->period);
+    const int32_t W = default_window(ctx, d, ctx->stims[stim]);
     std::vector<Piece> pieces;
     for (int32_t c0 = cycle_begin; c0 < cycle_end; c0 += W)
         pieces.push_back(make_piece(ctx, design, stim, c0, std::min(W, cycle_end - c0)));
@@ -569,7 +602,9 @@ extern "C" gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t st
 {
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
     if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
-    gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
+    gs_status st = gs_job_cycles(ctx, stim, cycle_begin, cycle_end);
+    if (st) return st;
+    st = check_job(ctx, design, stim, cycle_begin, cycle_end);
     if (st) return st;
     if (!ctx->d_scratch) return gs_fail(ctx, GS_E_STATE, "no static scratch on this device");
     (void)hipSetDevice(ctx->opt.device);
@@ -589,6 +624,12 @@ extern "C" gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t st
                        (unsigned long long)gs_header_bytes((uint64_t)d->N, kLanes), win_bytes);
     int32_t W = 16384;
     while (W > kLanes && gs_header_bytes((uint64_t)d->N, W) * 2 > win_bytes) W /= 2;
+    const int32_t S = ctx->stims[stim]->carry;
+    if (S > 0) {                                            // whole segments per window
+        W = std::max(1, W / S) * S;
+        if (gs_header_bytes((uint64_t)d->N, W) * 2 > win_bytes)
+            return gs_fail(ctx, GS_E_NOMEM, "the chunk headers of one %d-cycle segment outgrow the static scratch", S);
+    }
 
     struct Saved {
         gs_options opt;
@@ -682,6 +723,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t design, int32_t stim, int3
     if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving");
     gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
     if (st) return st;
+    if (ctx->stims[stim]->carry) return gs_fail(ctx, GS_E_INVALID, "tune on the stimulus, not its continuous view");
     if (cycle_end <= cycle_begin) return gs_fail(ctx, GS_E_INVALID, "empty trial range");
     (void)hipSetDevice(ctx->opt.device);
     std::vector<Piece> trial{make_piece(ctx, design, stim, cycle_begin, std::min(cycle_end - cycle_begin, 4096))};
@@ -704,10 +746,15 @@ extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job
     if (!ctx) return gs_fail(nullptr, GS_E_INVALID, "null context");
     if (ctx->serving) return gs_fail(ctx, GS_E_STATE, "context is serving; use gs_submit");
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return gs_fail(ctx, GS_E_INVALID, "bad job array");
+    // jobs on continuous views count segments: as cycle ranges from here on
+    std::vector<gs_job> cj(jobs, jobs + n_jobs);
     for (int32_t i = 0; i < n_jobs; i++) {
-        gs_status st = check_job(ctx, jobs[i].design, jobs[i].stim, jobs[i].cycle_begin, jobs[i].cycle_end);
+        gs_status st = gs_job_cycles(ctx, cj[i].stim, cj[i].cycle_begin, cj[i].cycle_end);
+        if (st) return st;
+        st = check_job(ctx, cj[i].design, cj[i].stim, cj[i].cycle_begin, cj[i].cycle_end);
         if (st) return st;
     }
+    jobs = cj.data();
     (void)hipSetDevice(ctx->opt.device);
     const uint64_t t_start = gs_now_ns();
     ctx->last = LastWindow();
@@ -715,7 +762,7 @@ extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job
     for (int32_t i = 0; i < n_jobs; i++) {
         const gs_job &j = jobs[i];
         Design *d = ctx->designs[j.design];
-        const int32_t W = default_window(ctx, d, ctx->stims[j.stim]->period);
+        const int32_t W = default_window(ctx, d, ctx->stims[j.stim]);
         for (int32_t c0 = j.cycle_begin; c0 < j.cycle_end; c0 += W)
             pieces.push_back(make_piece(ctx, j.design, j.stim, c0, std::min(W, j.cycle_end - c0)));
     }

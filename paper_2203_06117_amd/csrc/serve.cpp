@@ -268,7 +268,7 @@ gs_status start_request(gs_ctx *ctx, ServeState *S, Req &q, std::string &err)
     if (q.r.kind == GS_REQ_WINDOW) {
         SCHK(launch_fill_u64(q.acc.tc, kSaifArrays * (uint64_t)q.d->N, 0ull, hs));
         SCHK(launch_fill_u32((unsigned int *)q.d_c0, 1, (unsigned int)q.c0, hs));
-        StimView sv{q.s->d_init, q.s->d_tp, q.s->d_ts, q.d->I, q.s->period};
+        StimView sv{q.s->d_init, q.s->d_tp, q.s->d_ts, q.d->I, q.s->period, 0};
         SCHK(launch_expand(sv, q.view, q.acc, q.d_c0, (uint32_t)(S->salt++ * 131), hs));
     } else {
         const Resident &R = S->res[q.res_idx];
@@ -528,7 +528,7 @@ gs_status launch_step(gs_ctx *ctx, ServeState *S, std::vector<ReqP> &run, std::s
         std::memcpy(stage, segs[kind].data(), sizeof(Seg) * segs[kind].size());
         SCHK(hipMemcpyAsync(dst, stage, sizeof(Seg) * segs[kind].size(), hipMemcpyHostToDevice, S->st));
         SCHK(launch_gate_eval(dst, (int32_t)segs[kind].size(), waves[kind], wires[kind], ctx->opt.lds_cap,
-                              ctx->opt.waves_per_block, kmax[kind], tpw, kind, S->st));
+                              ctx->opt.waves_per_block, kmax[kind], tpw, kind, 0, S->st));
         SCHK(hipEventRecord(S->ring_ev[slot], S->st));
     }
     return GS_OK;
@@ -752,6 +752,7 @@ extern "C" gs_status gs_serve_start(gs_ctx *ctx, int32_t n_resident, const int32
         if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", designs[i]);
         if (stims[i] < 0 || stims[i] >= (int32_t)ctx->stims.size() || ctx->stims[stims[i]]->design != designs[i])
             return gs_fail(ctx, GS_E_INVALID, "stimulus %d does not belong to design %d", stims[i], designs[i]);
+        if (ctx->stims[stims[i]]->carry) return gs_fail(ctx, GS_E_INVALID, "continuous views are not served");
         if (resident_cycles[i] <= 0) return gs_fail(ctx, GS_E_INVALID, "resident window must be non-empty");
         gs_status st = gs_check_ranges(ctx, d, ctx->stims[stims[i]], resident_begin[i], resident_begin[i] + resident_cycles[i]);
         if (st) return st;
@@ -859,6 +860,7 @@ extern "C" gs_status gs_submit(gs_ctx *ctx, const gs_request *req, uint64_t *tic
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", req->design);
     if (req->stim < 0 || req->stim >= (int32_t)ctx->stims.size() || ctx->stims[req->stim]->design != req->design)
         return gs_fail(ctx, GS_E_INVALID, "stimulus %d does not belong to design %d", req->stim, req->design);
+    if (ctx->stims[req->stim]->carry) return gs_fail(ctx, GS_E_INVALID, "continuous views are not served");
     q->d = d;
     q->s = ctx->stims[req->stim];
     if (req->kind == GS_REQ_WINDOW) {

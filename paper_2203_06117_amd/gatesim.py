@@ -99,6 +99,7 @@ _SIGS = {
     "gs_load_wires": (I32, [P, I32, P, P]),
     "gs_load_stimulus": (I32, [P, I32, I32, I32, P, P, P, C.POINTER(I32)]),
     "gs_segment_stimulus": (I32, [P, I32, I32, C.POINTER(I32)]),
+    "gs_continuous_stimulus": (I32, [P, I32, I32, C.POINTER(I32)]),
     "gs_glitch_profile": (I32, [P, I32, I32, I32, I32, P]),
     "gs_cycle_profile": (I32, [P, I32, I32, I32, I32, P, P]),
     "gs_simulate": (I32, [P, I32, I32, I32, I32]),
@@ -287,6 +288,13 @@ class GateSim:
         cycles, each simulated continuously (returns the new stimulus id)."""
         s = I32()
         self._chk(_lib.gs_segment_stimulus(self._h, int(stim), int(segment_cycles), C.byref(s)))
+        return s.value
+
+    def continuous_stimulus(self, stim, segment_cycles) -> int:
+        """Like ``segment_stimulus`` (the same results), with one lane per
+        cycle and the pending edge carried from cycle to cycle."""
+        s = I32()
+        self._chk(_lib.gs_continuous_stimulus(self._h, int(stim), int(segment_cycles), C.byref(s)))
         return s.value
 
     def load_work(self, work: dict, cells_loaded: bool = False):
