@@ -12,6 +12,9 @@ Also reported (one JSON line):
                 library's stream) vs 8 TB/s, with the measured HBM traffic,
                 a per-sink byte model and a copy kernel's bandwidth
   windows_1000  the same workload in 1,000-cycle windows
+  continuous_1000  the same workload as continuous 1,000-cycle segments (one
+                lane per cycle, pending edges carried across cycle
+                boundaries), checked against the single-lane segment view
   cpu_baseline  the CPU oracle timed on bounded samples of the same workload:
                 one process per host core, and single-threaded (whose SAIF
                 also re-checks the GPU result)
@@ -215,6 +218,9 @@ def run_scale(args, torch, synth, GateSim):
                "gpu_parity_on_sample": parity}
     sim.close()
     windowed = run_scale_windows(args, torch, w, GateSim, b_min) if args.window_leg else None
+    continuous = run_continuous(args, torch, w, GateSim, windowed) if args.window_leg else None
+    if continuous:
+        continuous["headline_over_continuous"] = round(gate_cycles / elapsed / continuous["value"], 3)
     return {
         "value": round(gate_cycles / elapsed, 1),
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
@@ -231,6 +237,7 @@ def run_scale(args, torch, synth, GateSim):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "windows_1000": windowed,
+        "continuous_1000": continuous,
     }
 
 
@@ -299,6 +306,57 @@ def run_scale_windows(args, torch, w, GateSim, b_min):
             "kernel_gate_cycles_per_s": round(Gn * C * steps / (st["gate_eval_ms"] / 1e3), 1),
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
             "frac": round(b_min * gc_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def run_continuous(args, torch, w, GateSim, isolated):
+    """The same workload as continuous 1,000-cycle segments (edges and
+    pending events cross the cycle boundaries inside a segment) run with one
+    lane per cycle and the carried pending edge, beside the cycle-isolated
+    run in the same 1,000-cycle windows; the whole result is compared with
+    the single-lane segment view, which runs each segment as one lane, on
+    the first three segments."""
+    net, stim = w["netlist"], w["stimulus"]
+    Gn, C = net["n_gates"], stim["n_cycles"]
+    S = 1000
+    sim = GateSim(device=0, stream=torch.cuda.current_stream(), window_cycles=S, lds_cap=args.lds_cap,
+                  waves_per_block=args.wpb, timing=True, tiles_per_wave=args.tpw)
+    d, s = sim.load_work(w)
+    v = sim.continuous_stimulus(s, S)
+    sim.simulate(d, v, 0, C // S)
+    sim.read_saif(d, reset=True)
+    steps = max(1, min(args.steps, 3))
+    sim.stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.simulate(d, v, 0, C // S)
+        saif = sim.read_saif_ig(d, reset=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = sim.stats()
+    launches = st["gate_eval_launches"]
+    avg_s = st["gate_eval_ms"] / 1e3 / launches
+    # the first three segments again, and through the single-lane view
+    # (three lanes per chunk keep its per-chunk transition count in range)
+    k = min(3, C // S)
+    sim.simulate(d, v, 0, k)
+    part = sim.read_saif_ig(d, reset=True)
+    sv = sim.segment_stimulus(s, S)
+    tq = time.perf_counter()
+    sim.simulate(d, sv, 0, k)
+    single = sim.read_saif_ig(d, reset=True)
+    single_s = time.perf_counter() - tq
+    sim.close()
+    same = all(bool(np.array_equal(a, b)) for a, b in zip(part, single))
+    value = Gn * C * steps / elapsed
+    log(f"continuous {S}-cycle segments: {steps} steps in {elapsed:.3f}s, {avg_s * 1e6:.1f} us per launch, "
+        f"single-lane view {single_s:.1f}s, equal {same}")
+    return {"segment_cycles": S, "window_cycles": S, "steps": steps, "value": round(value, 1),
+            "unit": "gate-cycles/s", "ms_per_step": round(elapsed / steps * 1e3, 3),
+            "kernel_gate_cycles_per_s": round(Gn * C * steps / (st["gate_eval_ms"] / 1e3), 1),
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+            "isolated_1000_over_continuous": round(isolated["value"] / value, 3) if isolated else None,
+            "single_lane_segments": k, "single_lane_view_s": round(single_s, 2), "equals_single_lane_view": same}
 
 
 def run_glitchy(args, torch, synth, GateSim):

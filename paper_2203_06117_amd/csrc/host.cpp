@@ -854,13 +854,16 @@ extern "C" gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim,
     Design *d = gs_get_design(ctx, design);
     if (!d) return gs_fail(ctx, GS_E_INVALID, "no design %d", design);
     if (net < 0 || net >= d->N) return gs_fail(ctx, GS_E_INVALID, "net %d out of range", net);
-    const LastWindow &lw = ctx->last;
     // a continuous view's segment is the concatenation of its cycles' lists
     const Stim *sv = (stim >= 0 && stim < (int32_t)ctx->stims.size()) ? ctx->stims[stim] : nullptr;
     const int32_t S = sv && sv->carry > 0 ? sv->carry : 1;
     const int64_t c_first = (int64_t)cycle * S;
-    if (lw.design != design || lw.stim != stim || cycle < 0 || c_first < lw.c0 || c_first + S > (int64_t)lw.c0 + lw.cycles)
-        return gs_fail(ctx, GS_E_STATE, "cycle %d of (design %d, stim %d) is not resident", cycle, design, stim);
+    const LastWindow *found = nullptr;
+    for (const LastWindow &w : ctx->last)
+        if (w.design == design && w.stim == stim && cycle >= 0 && c_first >= w.c0 && c_first + S <= (int64_t)w.c0 + w.cycles)
+            found = &w;
+    if (!found) return gs_fail(ctx, GS_E_STATE, "cycle %d of (design %d, stim %d) is not resident", cycle, design, stim);
+    const LastWindow &lw = *found;
     if (S > 1 && (int64_t)S * sv->period + (int64_t)(d->L + 1) * d->max_delay >= (int64_t)kInf)
         return gs_fail(ctx, GS_E_INVALID, "segment times exceed int32 picoseconds");
     (void)hipSetDevice(ctx->opt.device);

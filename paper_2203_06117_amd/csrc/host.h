@@ -125,7 +125,7 @@ struct gs_ctx {
     std::vector<Design *> designs;
     std::vector<Stim *> stims;
     WindowBufs win;
-    LastWindow last;
+    std::vector<LastWindow> last;            // the windows of the last round, readable by gs_read_waveform
     gs::Seg *d_segs = nullptr;
     size_t segs_cap = 0;
     unsigned long long *d_misc = nullptr;    // [0] unused, [1] flags x2 (u32), [2] flags, [4..] scratch counters

@@ -1390,12 +1390,31 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             // carry changes.  The carry chain runs upwards through the lanes
             // and each pass settles at least the lowest lane still open, so
             // this ends within 64 passes.
-            int32_t cin = -1, cfull = 0;
-            bool cout_taken = false;
+            // A lane with a carry-in W whose first pin event comes no
+            // earlier than W evolves as its first walk did, after the
+            // pending edge has matured (no event meets it, and the walk's
+            // own decisions read the same values), so its list is W followed
+            // by that walk's list: it is not walked again (`pre` = W).
+            int32_t cin = -1, pre = -1, nlds = cnt;
+            bool cout_taken = false, cout_pre = false;
             if constexpr (CONT) {
                 const uint32_t p = (uint32_t)lc % seg_len;
                 const bool sstart = p == 0, send = p == seg_len - 1;
-                auto cout_of = [&]() { return (active && !send && cnt > 0 && wl >= T) ? wl - T : -1; };
+                int32_t tfirst = kInf;                          // the lane's first pin event
+#pragma unroll
+                for (int j = 0; j < K; j++) {
+                    if (lo[j] < hi[j]) {
+                        const int32_t e = staged ? gs_lds[base[j] + lo[j]]
+                                                 : ld_word(win.times + readlane64(c_off, (uint32_t)j * GT + u), lo[j]);
+                        tfirst = min(tfirst, e);
+                    }
+                }
+                const int32_t cnt_s = cnt, wl_s = wl, acc_s = acc;   // the first walk
+                bool spec = true;                               // LDS slots and acc hold the first walk
+                auto cout_of = [&]() {
+                    const int32_t last = cnt > 0 ? wl : pre;
+                    return (active && !send && last >= T) ? last - T : -1;
+                };
                 int32_t co = cout_of();
                 for (uint32_t pass = 0;; pass++) {
                     int32_t ni = (int32_t)wave_shr1((uint32_t)(co + 1)) - 1;
@@ -1410,19 +1429,34 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     }
                     if (redo) {
                         cin = ni;
-                        acc = 0;
-                        run(cin);
+                        if (spec && tfirst >= ni) {             // also ni < 0: the first walk stands
+                            pre = ni;
+                            cnt = cnt_s;
+                            wl = wl_s;
+                            acc = acc_s;
+                        } else {
+                            pre = -1;
+                            acc = 0;
+                            run(ni);
+                            spec = ni < 0;
+                        }
                         co = cout_of();
                     }
                 }
                 carry = __builtin_amdgcn_readlane(co, kLanes - 1);
-                cfull = cnt;
+                nlds = cnt;
                 cout_taken = co >= 0;
-                if (cout_taken) cnt--;
+                if (cout_taken) {
+                    if (cnt > 0) cnt--;                         // the walk's last edge leaves
+                    else {
+                        pre = -1;                               // the carried-in edge passes through
+                        cout_pre = true;
+                    }
+                }
             }
             const int yi = y0 ^ (cin >= 0 ? 1 : 0);         // the output's value at t = 0
 
-            const uint32_t ucnt = (uint32_t)cnt;
+            const uint32_t ucnt = (uint32_t)cnt + (pre >= 0 ? 1u : 0u);    // the lane's final list
             const uint32_t incl = wave_incl_scan(ucnt);
             const uint32_t total = (uint32_t)lane63(incl);
             const uint64_t mask = __ballot(active && yi);
@@ -1462,26 +1496,34 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             const uint32_t first = wave_shr1(incl);            // exclusive prefix: the lane's first slot
             int32_t *out = out_chunk + first;
             const int32_t n = cnt < CAP ? cnt : CAP;
-            bool walk_acc = !staged;                            // acc holds the walk's own sum of every edge
+            bool walk_acc = !staged;                            // acc holds a walk's own sum of its edges
             {
                 int v = yi;
                 int32_t s1 = 0;
+                uint32_t o = first;
+                if (CONT && pre >= 0) {                         // the prepended carried-in edge
+                    if (ok) st_word(out_chunk, o, pre);
+                    o++;
+                    v ^= 1;
+                    const int32_t ce = min(pre, T);
+                    s1 += v ? -ce : ce;
+                    if (!staged) acc += v ? -ce : ce;           // the first walk's sum lacks it
+                }
                 for (int32_t i = 0; i < n; i++) {
                     const int32_t e = gs_lds[out_lane + i * kLanes];
-                    if (ok) st_word(out_chunk, first + (uint32_t)i, e);
+                    if (ok) st_word(out_chunk, o + (uint32_t)i, e);
                     v ^= 1;
                     const int32_t ce = min(e, T);
                     s1 += v ? -ce : ce;
                 }
                 if (staged) acc = s1;
             }
-            const int32_t nwalk = CONT ? cfull : cnt;          // the walk's count, with a carried-out edge
-            const uint64_t spill = __ballot(nwalk > CAP);
+            const uint64_t spill = __ballot(nlds > CAP);
             if (spill) {
                 // lanes whose list outgrew the staging walk again, from the
                 // arena, writing to their place in the output chunk (and
-                // returning the complete T1 sum)
-                if (nwalk > CAP) {
+                // returning the complete T1 sum; a carried-in edge is its seed)
+                if (nlds > CAP) {
                     Cursor<K, WIRES, false> P;
 #pragma unroll
                     for (int j = 0; j < K; j++) {
@@ -1492,8 +1534,8 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     P.state = state0;
                     P.transport = transport;
                     int32_t c2, z2, w2;
-                    walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, ok ? cnt : 0, cin, c2, acc,
-                                                  z2, w2);
+                    walk<K, WIRES, false, 1, CAP>(P, arc, g.truth, T, y0, lut_base, 0, out, ok ? (int32_t)ucnt : 0,
+                                                  cin, c2, acc, z2, w2);
                     walk_acc = true;
                 }
                 if (lane == 0 && ok)
@@ -1502,8 +1544,8 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             }
             // a walk's sum counted the edge carried out of the cycle (at or
             // after T, so it added -T after a rise and +T after a fall)
-            if (CONT && cout_taken && walk_acc) acc -= ((yi ^ (cfull & 1)) != 0) ? -T : T;
-            z = yi ^ (cnt & 1);                      // every kept edge toggles the output
+            if (CONT && cout_taken && !cout_pre && walk_acc) acc -= ((yi ^ ((ucnt + 1) & 1)) != 0) ? -T : T;
+            z = yi ^ (int)(ucnt & 1u);               // every kept edge toggles the output
             tc_sum += total;
             if constexpr (CONT) {
                 // a segment's glitch toggles: its edges less the parity of

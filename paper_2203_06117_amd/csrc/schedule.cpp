@@ -320,14 +320,18 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     ctx->stats.gate_eval_launches += res.launches;
     ctx->stats.windows += (int64_t)pieces.size();
     for (const Piece &p : pieces) ctx->stats.gate_cycles += (int64_t)p.d->G * p.cycles;
-    // the last piece stays readable through gs_read_waveform
-    const Piece &lp = pieces.back();
-    ctx->last.design = lp.di;
-    ctx->last.stim = lp.si;
-    ctx->last.c0 = lp.c0;
-    ctx->last.cycles = lp.cycles;
-    ctx->last.chunk_base = lp.chunk_base;
-    ctx->last.n_nets = lp.d->N;
+    // the round's windows stay readable through gs_read_waveform
+    ctx->last.clear();
+    for (const Piece &p : pieces) {
+        LastWindow lw;
+        lw.design = p.di;
+        lw.stim = p.si;
+        lw.c0 = p.c0;
+        lw.cycles = p.cycles;
+        lw.chunk_base = p.chunk_base;
+        lw.n_nets = p.d->N;
+        ctx->last.push_back(lw);
+    }
     return GS_OK;
 }
 
@@ -458,11 +462,16 @@ int32_t window_cycles(gs_ctx *ctx, const Design *d, int32_t period)
     return W;
 }
 
-// The same for a stimulus: a continuous view's windows hold whole segments.
+// The same for a stimulus.  A continuous view's windows hold whole
+// segments.  Where segments do not tile 64 cycles, a wave takes a whole
+// window, so windows are kept near 1,024 cycles (or one segment) and run
+// several to a round, which keeps launches wide.
 int32_t default_window(gs_ctx *ctx, const Design *d, const Stim *s)
 {
-    const int32_t W = window_cycles(ctx, d, s->period);
-    return s->carry > 0 ? std::max(1, W / s->carry) * s->carry : W;
+    const int32_t W = window_cycles(ctx, d, s->period), S = s->carry;
+    if (S <= 0) return W;
+    if (kLanes % S != 0) return std::min(std::max(1, W / S), std::max(1, 1024 / S)) * S;
+    return std::max(1, W / S) * S;
 }
 
 gs_status check_job(gs_ctx *ctx, int32_t design, int32_t stim, int32_t b, int32_t e)
@@ -563,7 +572,7 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
     if (st) return st;
     (void)hipSetDevice(ctx->opt.device);
     const uint64_t t_start = gs_now_ns();
-    ctx->last = LastWindow();
+    ctx->last.clear();
     Design *d = ctx->designs[design];
     // a design's first run learns its transition density from a 64-cycle
     // pilot (nothing committed), so that the arena of the real windows is
@@ -576,14 +585,21 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
                         8ull * (uint64_t)d->N * kLanes);
         if (st) return st;
     }
-    const int32_t W = default_window(ctx, d, ctx->stims[stim]);
+    const Stim *sm = ctx->stims[stim];
+    const int32_t W = default_window(ctx, d, sm);
     std::vector<Piece> pieces;
     for (int32_t c0 = cycle_begin; c0 < cycle_end; c0 += W)
         pieces.push_back(make_piece(ctx, design, stim, c0, std::min(W, cycle_end - c0)));
-    // one window per round: windows run one after another
-    for (const Piece &p : pieces) {
-        st = run_pieces(ctx, std::vector<Piece>{p}, tuning_for(ctx, {p}), true, ctx->opt.timing != 0, nullptr);
+    if (sm->carry > 0 && kLanes % sm->carry != 0) {
+        // a continuous view's short windows: as many to a round as fit
+        st = run_pieces(ctx, pieces, tuning_for(ctx, pieces), true, ctx->opt.timing != 0, nullptr);
         if (st) return st;
+    } else {
+        // one window per round: windows run one after another
+        for (const Piece &p : pieces) {
+            st = run_pieces(ctx, std::vector<Piece>{p}, tuning_for(ctx, {p}), true, ctx->opt.timing != 0, nullptr);
+            if (st) return st;
+        }
     }
     ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
     return GS_OK;
@@ -671,7 +687,7 @@ extern "C" gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t st
     ctx->segs_cap = sv.segs_cap;
     ctx->d_c0 = sv.c0;
     ctx->c0_cap = sv.c0_cap;
-    ctx->last = LastWindow();                  // the scratch window is not kept for gs_read_waveform
+    ctx->last.clear();                  // the scratch window is not kept for gs_read_waveform
     ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
     return st;
 }
@@ -757,7 +773,7 @@ extern "C" gs_status gs_simulate_batch(gs_ctx *ctx, int32_t n_jobs, const gs_job
     jobs = cj.data();
     (void)hipSetDevice(ctx->opt.device);
     const uint64_t t_start = gs_now_ns();
-    ctx->last = LastWindow();
+    ctx->last.clear();
     std::vector<Piece> pieces;
     for (int32_t i = 0; i < n_jobs; i++) {
         const gs_job &j = jobs[i];
