@@ -1380,25 +1380,31 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                                                   z, wl);
                 }
             };
-            run(-1);
             // Continuous segments: a lane's list keeps the edges before the
             // end of its cycle; the one edge still pending there (at most
             // one, Algorithm 1 cancels a pending edge rather than queueing a
             // second) moves to the next cycle of the segment, which starts
-            // with it pending.  Every lane first ran as if nothing were
-            // pending; lanes whose carry-in differs run again until no
-            // carry changes.  The carry chain runs upwards through the lanes
-            // and each pass settles at least the lowest lane still open, so
-            // this ends within 64 passes.
+            // with it pending.  Every lane first walks as if nothing were
+            // pending; lanes whose carry-in differs are evaluated again until
+            // no carry changes.  The carry chain runs upwards through the
+            // lanes and each pass settles at least the lowest lane still
+            // open, so this ends within 64 passes.
             // A lane with a carry-in W whose first pin event comes no
             // earlier than W evolves as its first walk did, after the
             // pending edge has matured (no event meets it, and the walk's
             // own decisions read the same values), so its list is W followed
             // by that walk's list: it is not walked again (`pre` = W).
-            int32_t cin = -1, pre = -1, nlds = cnt;
+            int32_t cin = -1, pre = -1, nlds = 0;
             bool cout_taken = false, cout_pre = false;
-            if constexpr (CONT) {
-                const uint32_t p = (uint32_t)lc % seg_len;
+            uint32_t p = 0;                                     // the lane's cycle within its segment
+            if constexpr (!CONT) {
+                run(-1);
+                nlds = cnt;
+            } else {
+                const uint32_t p0 = (tile * kLanes) % seg_len;  // uniform
+                p = p0 + (uint32_t)lane;
+                if (seg_len >= (uint32_t)kLanes) p = p >= seg_len ? p - seg_len : p;
+                else p %= seg_len;
                 const bool sstart = p == 0, send = p == seg_len - 1;
                 int32_t tfirst = kInf;                          // the lane's first pin event
 #pragma unroll
@@ -1409,14 +1415,23 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                         tfirst = min(tfirst, e);
                     }
                 }
-                const int32_t cnt_s = cnt, wl_s = wl, acc_s = acc;   // the first walk
+                int32_t cnt_s = 0, wl_s = 0, acc_s = 0;         // the first walk
                 bool spec = true;                               // LDS slots and acc hold the first walk
-                auto cout_of = [&]() {
-                    const int32_t last = cnt > 0 ? wl : pre;
-                    return (active && !send && last >= T) ? last - T : -1;
-                };
-                int32_t co = cout_of();
+                bool walk_now = true;
+                int32_t seed = -1, co = -1;
                 for (uint32_t pass = 0;; pass++) {
+                    if (walk_now) {
+                        acc = 0;
+                        run(seed);
+                        spec = seed < 0;
+                    }
+                    if (pass == 0) {
+                        cnt_s = cnt;
+                        wl_s = wl;
+                        acc_s = acc;
+                    }
+                    const int32_t last = cnt > 0 ? wl : pre;
+                    co = (active && !send && last >= T) ? last - T : -1;
                     int32_t ni = (int32_t)wave_shr1((uint32_t)(co + 1)) - 1;
                     if (lane == 0) ni = carry;
                     if (sstart || !active) ni = -1;
@@ -1427,6 +1442,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                             __hip_atomic_fetch_or(glob(win.flags + 3), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
+                    walk_now = false;
                     if (redo) {
                         cin = ni;
                         if (spec && tfirst >= ni) {             // also ni < 0: the first walk stands
@@ -1436,11 +1452,9 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                             acc = acc_s;
                         } else {
                             pre = -1;
-                            acc = 0;
-                            run(ni);
-                            spec = ni < 0;
+                            seed = ni;
+                            walk_now = true;
                         }
-                        co = cout_of();
                     }
                 }
                 carry = __builtin_amdgcn_readlane(co, kLanes - 1);
@@ -1550,8 +1564,8 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             if constexpr (CONT) {
                 // a segment's glitch toggles: its edges less the parity of
                 // their number, which is its start value XOR its end value
-                const uint64_t ms = __ballot(active && (uint32_t)lc % seg_len == 0);
-                const uint64_t me = __ballot(active && (uint32_t)lc % seg_len == seg_len - 1);
+                const uint64_t ms = __ballot(active && p == 0);
+                const uint64_t me = __ballot(active && p == seg_len - 1);
                 const uint64_t mi = __ballot(yi != 0), mf = __ballot(z != 0);
                 uint32_t odd = 0;
                 for (uint64_t b = ms | me; b; b &= b - 1) {

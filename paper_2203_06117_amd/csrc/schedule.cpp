@@ -312,9 +312,11 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
                                         (uint32_t)p.cycles, p.s->period, ctx->d_profile ? ctx->d_profile + at : nullptr,
                                         ctx->d_late ? ctx->d_late + at : nullptr, hs));
         }
-    if (pieces.size() == 1 && pieces[0].cycles > 0)       // learn the design's list density
-        pieces[0].d->words_per_ps = (double)used / ((double)std::max(1, pieces[0].d->N) * pieces[0].cycles *
-                                                    (double)pieces[0].s->period);
+    // learn the design's list density from rounds of one design
+    double lane_ps = 0;
+    for (const Piece &p : pieces) lane_ps += (double)p.cycles * (double)p.s->period;
+    if (designs.size() == 1 && lane_ps > 0)
+        designs[0]->words_per_ps = (double)used / ((double)std::max(1, designs[0]->N) * lane_ps);
     ctx->stats.gate_eval_ms += res.gate_eval_ms;
     ctx->stats.expand_ms += res.expand_ms;
     ctx->stats.gate_eval_launches += res.launches;
@@ -590,17 +592,10 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
     std::vector<Piece> pieces;
     for (int32_t c0 = cycle_begin; c0 < cycle_end; c0 += W)
         pieces.push_back(make_piece(ctx, design, stim, c0, std::min(W, cycle_end - c0)));
-    if (sm->carry > 0 && kLanes % sm->carry != 0) {
-        // a continuous view's short windows: as many to a round as fit
-        st = run_pieces(ctx, pieces, tuning_for(ctx, pieces), true, ctx->opt.timing != 0, nullptr);
-        if (st) return st;
-    } else {
-        // one window per round: windows run one after another
-        for (const Piece &p : pieces) {
-            st = run_pieces(ctx, std::vector<Piece>{p}, tuning_for(ctx, {p}), true, ctx->opt.timing != 0, nullptr);
-            if (st) return st;
-        }
-    }
+    // windows are independent: as many to a round (one launch per level
+    // for all of them) as the budget holds
+    st = run_pieces(ctx, pieces, tuning_for(ctx, pieces), true, ctx->opt.timing != 0, nullptr);
+    if (st) return st;
     ctx->stats.wall_ms += (gs_now_ns() - t_start) * 1e-6;
     return GS_OK;
 }
