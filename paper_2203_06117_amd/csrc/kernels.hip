@@ -1346,12 +1346,36 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 lo[j] = wave_shr1(hi[j]);
                 state0 |= ((ev[j][0] >> kEndInitShift) & 1u) << j;
             }
+            // A group too large for the stage whose tile alone fits it: the
+            // tile's fanin chunks are copied in, so that its walk reads LDS
+            // too (its output words are still reserved per tile).
+            bool lstaged = staged;
+            if (!staged) {
+                uint32_t tn[K], tsum = 0;
+#pragma unroll
+                for (int j = 0; j < K; j++) {
+                    tn[j] = (uint32_t)__builtin_amdgcn_readlane((int)c_tot, j * (int)GT + (int)u);
+                    tsum += tn[j];
+                }
+                if (tsum <= kStageWords) {
+                    uint32_t pos = stage_base;
+#pragma unroll
+                    for (int j = 0; j < K; j++) {
+                        base[j] = pos;
+                        const int32_t *src = win.times + readlane64(c_off, (uint32_t)j * GT + u);
+                        for (uint32_t r = (uint32_t)lane; r < tn[j]; r += kLanes) gs_lds[pos + r] = ld_word(src, r);
+                        pos += tn[j];
+                    }
+                    wave_lds_sync();
+                    lstaged = true;
+                }
+            }
             const int y0 = (int)((g.truth >> state0) & 1);     // zero-delay settled value at t = 0
             int32_t cnt = 0, acc = 0, z = 0, wl = 0;
             // the lane's walk; seed >= 0: an output edge to y0 pending there
             // at t = 0 (continuous segments only)
             auto run = [&](int32_t seed) {
-                if (staged) {
+                if (lstaged) {
                     Cursor<K, false, true> P;
 #pragma unroll
                     for (int j = 0; j < K; j++) {
@@ -1410,7 +1434,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
 #pragma unroll
                 for (int j = 0; j < K; j++) {
                     if (lo[j] < hi[j]) {
-                        const int32_t e = staged ? gs_lds[base[j] + lo[j]]
+                        const int32_t e = lstaged ? gs_lds[base[j] + lo[j]]
                                                  : ld_word(win.times + readlane64(c_off, (uint32_t)j * GT + u), lo[j]);
                         tfirst = min(tfirst, e);
                     }
@@ -1510,7 +1534,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
             const uint32_t first = wave_shr1(incl);            // exclusive prefix: the lane's first slot
             int32_t *out = out_chunk + first;
             const int32_t n = cnt < CAP ? cnt : CAP;
-            bool walk_acc = !staged;                            // acc holds a walk's own sum of its edges
+            bool walk_acc = !lstaged;                           // acc holds a walk's own sum of its edges
             {
                 int v = yi;
                 int32_t s1 = 0;
@@ -1521,7 +1545,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     v ^= 1;
                     const int32_t ce = min(pre, T);
                     s1 += v ? -ce : ce;
-                    if (!staged) acc += v ? -ce : ce;           // the first walk's sum lacks it
+                    if (!lstaged) acc += v ? -ce : ce;          // the first walk's sum lacks it
                 }
                 for (int32_t i = 0; i < n; i++) {
                     const int32_t e = gs_lds[out_lane + i * kLanes];
@@ -1530,7 +1554,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                     const int32_t ce = min(e, T);
                     s1 += v ? -ce : ce;
                 }
-                if (staged) acc = s1;
+                if (lstaged) acc = s1;
             }
             const uint64_t spill = __ballot(nlds > CAP);
             if (spill) {
