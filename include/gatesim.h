@@ -105,7 +105,16 @@ typedef struct {
                                  delays): every net edge reaches the pin at its time plus the wire delay of its
                                  direction, and a pulse vanishes only when its delayed trailing edge arrives no
                                  later than its delayed leading edge; 0 = the inertial filter */
-    int32_t  reserved[4];
+    int32_t  release_dead;    /* nonzero: gs_simulate keeps a net's transitions only until the last level that
+                                 reads them (Section 3's preallocated waveform memory, with the space of dead
+                                 nets reused): the window's arena is split into one region per such level,
+                                 placed by the host so that a region is reused only after its level has run,
+                                 and sized from the design's learned density (a region that fills up is grown
+                                 and the round rerun).  Lets a window hold more cycles for the same budget;
+                                 gs_read_waveform and gs_cycle_profile then refuse the call (GS_E_STATE,
+                                 GS_E_INVALID), and gs_simulate_batch, gs_simulate_noalloc and serving keep
+                                 every net.  0 = every net stays until the window ends */
+    int32_t  reserved[3];
 } gs_options;
 
 /* Fills *opt with the defaults above. */
@@ -276,7 +285,7 @@ gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_b
  * overlap on one GPU (other threads or contexts) race.  gs_read_waveform
  * does not see windows run by this call.  Errors: as gs_simulate, and
  * GS_E_NOMEM when a 64-cycle window of the design (144 bytes per net) or its
- * levels (at most 6,241) do not fit the scratch. */
+ * levels (at most 5,957) do not fit the scratch. */
 #define GS_SCRATCH_BYTES (64ull << 20)
 gs_status gs_simulate_noalloc(gs_ctx *ctx, int32_t design, int32_t stim, int32_t cycle_begin, int32_t cycle_end);
 
@@ -331,7 +340,9 @@ typedef struct {
     int64_t  queue_overflows;   /* staged tile groups of gates with up to three pins that had more lanes with
                                    two or more pin events than the compacted walk queues, and took the per-tile
                                    walk instead */
-    int64_t  reserved[3];
+    int64_t  release_peak_words; /* with release_dead: arena words the last round's regions took at their peak
+                                   (arena_words counts every transition the round stored) */
+    int64_t  reserved[2];
 } gs_stats;
 
 gs_status gs_get_stats(gs_ctx *ctx, gs_stats *st, int32_t reset);

@@ -6,6 +6,7 @@
 #include "host.h"
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -336,6 +337,8 @@ extern "C" gs_status gs_destroy(gs_ctx *ctx)
     gs_dev_free(ctx->d_segs);
     gs_dev_free(ctx->d_misc);
     gs_dev_free(ctx->d_bump);
+    gs_dev_free(ctx->d_regions);
+    gs_dev_free(ctx->d_rbump);
     for (auto &ev : ctx->events) (void)hipEventDestroy(ev);
     gs_graph_cache_clear(ctx);
     gs_dev_free(ctx->d_c0);
@@ -490,12 +493,48 @@ static gs_status pack_design(gs_ctx *ctx, Design *d)
     const int32_t G = d->G;
     std::vector<GateRec> gates(std::max(1, G));
     std::vector<PinRec> pins(std::max<int64_t>(1, d->F));
+    // the last level that reads each gate output (its own level if none)
+    std::vector<int32_t> dead(G);
+    for (int32_t g = 0; g < G; g++) dead[g] = d->level[g];
+    for (int32_t g = 0; g < G; g++)
+        for (int64_t s = d->fanin_ptr[g]; s < d->fanin_ptr[g + 1]; s++) {
+            const int32_t n = d->fanin_net[s];
+            if (n >= d->I) dead[n - d->I] = std::max(dead[n - d->I], d->level[g]);
+        }
+    // Arena regions for the release of dead nets: region 0 holds the inputs;
+    // a gate output goes to the region of its level and of its last reading
+    // level rounded down to a multiple of q (at most 16 such classes per
+    // level), so that a region's nets are written by one launch and its space
+    // can be reused once the last of them has been read.
+    const int32_t q = std::max(1, (d->L + 15) / 16);
+    std::map<std::pair<int32_t, int32_t>, int32_t> region_of;
+    std::vector<int32_t> gate_region(G);
+    d->region_nets.assign(1, d->I);
+    d->region_first.assign(1, 0);
+    d->region_last.assign(1, INT32_MAX);
+    for (int32_t g = 0; g < G; g++) {
+        const auto key = std::make_pair(d->level[g], dead[g] / q);
+        auto it = region_of.find(key);
+        if (it == region_of.end()) {
+            it = region_of.emplace(key, (int32_t)d->region_nets.size()).first;
+            d->region_nets.push_back(0);
+            d->region_first.push_back(d->level[g]);
+            d->region_last.push_back(0);
+        }
+        const int32_t k = it->second;
+        gate_region[g] = k;
+        d->region_nets[k]++;
+        d->region_last[k] = std::max(d->region_last[k], dead[g]);
+    }
+    d->region_wpp.assign(d->region_nets.size(), 0.0);
+    d->region_grow.assign(d->region_nets.size(), 1.0);
     uint32_t pc = 0;
     for (int32_t p = 0; p < G; p++) {
         const int32_t g = d->perm[p];
         GateRec &r = gates[p];
         std::memset(&r, 0, sizeof(r));
         r.out = (uint32_t)(d->I + g);
+        r.dead = (uint32_t)gate_region[g];
         r.pin0 = pc;
         r.k = d->gate_k[g];
         r.truth = d->gate_truth[g];
@@ -862,6 +901,8 @@ extern "C" gs_status gs_read_waveform(gs_ctx *ctx, int32_t design, int32_t stim,
     for (const LastWindow &w : ctx->last)
         if (w.design == design && w.stim == stim && cycle >= 0 && c_first >= w.c0 && c_first + S <= (int64_t)w.c0 + w.cycles)
             found = &w;
+    if (!found && ctx->last_released)
+        return gs_fail(ctx, GS_E_STATE, "waveforms are not kept when dead nets are released (gs_options.release_dead)");
     if (!found) return gs_fail(ctx, GS_E_STATE, "cycle %d of (design %d, stim %d) is not resident", cycle, design, stim);
     const LastWindow &lw = *found;
     if (S > 1 && (int64_t)S * sv->period + (int64_t)(d->L + 1) * d->max_delay >= (int64_t)kInf)

@@ -66,6 +66,14 @@ struct Design {
     // this design alone (a segment view's lanes are longer); the window
     // planner and the arena guess size windows from it
     double words_per_ps = 0;
+    // release of dead nets: arena regions (0: the inputs; then one per level
+    // and class of last reading level, GateRec::dead); per region its net
+    // count, the level that writes it, the last level that reads one of its
+    // nets, and, learned, its transition words per net and picosecond and a
+    // growth factor raised each time it filled up
+    std::vector<int64_t> region_nets;
+    std::vector<int32_t> region_first, region_last;
+    std::vector<double> region_wpp, region_grow;
     // device
     int64_t *d_fanin_ptr = nullptr;
     int32_t *d_fanin_net = nullptr;
@@ -130,6 +138,14 @@ struct gs_ctx {
     size_t segs_cap = 0;
     unsigned long long *d_misc = nullptr;    // [0] unused, [1] flags x2 (u32), [2] flags, [4..] scratch counters
     unsigned long long *d_bump = nullptr;    // kMaxStripes stripe counters, kBumpStride apart
+    // release of dead nets (gs_simulate with opt.release_dead): set while
+    // gs_simulate runs; the region table and the regions' stripe counters
+    bool releasing = false;
+    bool last_released = false;              // the last round reused the space of dead nets
+    gs::ArenaRegion *d_regions = nullptr;
+    size_t regions_cap = 0;
+    unsigned long long *d_rbump = nullptr;
+    size_t rbump_cap = 0;                    // u64 counters
     std::vector<hipEvent_t> events;
     gs_stats stats{};
     // captured rounds, keyed by everything their launches depend on

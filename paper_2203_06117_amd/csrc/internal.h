@@ -50,7 +50,8 @@ struct GateRec {
     uint32_t out;       // output net id
     uint32_t pin0;      // index of its first PinRec
     uint32_t k;         // number of pins
-    uint32_t pad;
+    uint32_t dead;      // the output's arena region when dead nets are released (by its level and the
+                        // last level that reads it)
     uint64_t truth;     // truth bits, pin 0 = least significant bit of the index
     uint64_t pad2;
 };
@@ -75,6 +76,18 @@ struct PinRec {
 struct ChunkHdr {
     uint64_t off;
     uint64_t mask;
+};
+
+// One region of a window's transition arena when dead nets are released:
+// the chunks of nets written by one level and last read by about the same
+// level (region 0: the inputs), with its own stripe counters.  The host
+// places regions so that one is reused only after its last reader has run.
+struct ArenaRegion {
+    uint64_t off;                  // first word, counted from `times`
+    uint64_t slice_words;          // words per stripe
+    unsigned long long *bump;      // its stripe counters, kBumpStride apart
+    uint32_t stripe_mask;
+    uint32_t pad;
 };
 
 // A window of cycles resident on the device.
@@ -103,6 +116,10 @@ struct WinView {
     const int32_t *slot;
     const ChunkHdr *rd_hdr;
     const uint16_t *rd_ends;
+    // Release of dead nets: when set, region GateRec::dead of this table
+    // (region 0 for the inputs) replaces arena_off, slice_words, bump and
+    // stripe_mask for a producer's reservations.
+    const ArenaRegion *regions;
 };
 
 // The transition arena is split into stripes, each with its own bump

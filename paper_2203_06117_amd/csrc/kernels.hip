@@ -290,17 +290,17 @@ hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n
 
 // --------------------------------------------------------------------------
 // Arena reservation.  A wave reserves the words of its output chunks with
-// one atomic on its stripe's counter.  When that stripe is full, a few other
-// stripes spread over the arena are tried before the round is flagged for a
-// retry (flags[0]), so one full stripe does not fail a round while others
-// have room.  A failed try leaves its counter past the stripe's end (taking
+// one atomic on its stripe's counter.  When that stripe is full, up to 15
+// other stripes spread over the arena (every stripe of a region with 16) are
+// tried before the round is flagged for a retry (flags[0]), so one full
+// stripe does not fail a round while others have room.  A failed try leaves its counter past the stripe's end (taking
 // the words back could hand one range out twice while other waves reserve)
 // and adds its words to the stripe's second counter, so that the host can
 // tell the words handed out from the words lost to failed tries.  Returns
 // the reservation's first word, counted from the window's `times`, or ~0
 // when no try succeeded.
 // --------------------------------------------------------------------------
-constexpr uint32_t kStripeTries = 4;
+constexpr uint32_t kStripeTries = 16;
 
 __device__ __forceinline__ uint64_t arena_reserve(const WinView &win, uint32_t stripe0, uint32_t n, int lane)
 {
@@ -371,6 +371,13 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
 {
     extern __shared__ uint32_t ex_hist[];                   // kExpandGroup * 64 counters per wave
     const int32_t cycle0 = *glob(cycle0_p);
+    if (win.regions) {                                      // region 0 holds the inputs (dead nets released)
+        const ArenaRegion r = *kons(win.regions);
+        win.arena_off = r.off;
+        win.slice_words = r.slice_words;
+        win.bump = r.bump;
+        win.stripe_mask = r.stripe_mask;
+    }
     const int lane = threadIdx.x & (kLanes - 1);
     const uint32_t wib = uniform(threadIdx.x / kLanes);
     const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + wib;
@@ -1162,7 +1169,14 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
 {
     static_assert(!(CONT && (WIRES || REMAP)), "continuous segments: designs without interconnect delays, whole windows");
     constexpr uint32_t GT = K <= 3 ? 4 : 2;
-    const WinView &win = sg.win;
+    WinView win = sg.win;
+    if (win.regions) {                          // the output's region of the arena (dead nets released)
+        const ArenaRegion r = *kons(win.regions + g.dead);
+        win.arena_off = r.off;
+        win.slice_words = r.slice_words;
+        win.bump = r.bump;
+        win.stripe_mask = r.stripe_mask;
+    }
     const bool transport = (sg.mode & 1u) != 0;
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;

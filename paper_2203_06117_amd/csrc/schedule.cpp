@@ -12,7 +12,7 @@
 using namespace gs;
 
 static_assert(kScratchBytes == GS_SCRATCH_BYTES, "the public scratch size and the device array differ");
-static_assert(sizeof(Seg) == 168, "segment table capacity of the static scratch is documented for 168-byte segments");
+static_assert(sizeof(Seg) == 176, "segment table capacity of the static scratch is documented for 176-byte segments");
 
 #define HIPCHK(x)                                                                                  \
     do {                                                                                           \
@@ -84,6 +84,116 @@ uint64_t chunks_of(const Piece &p)
     return (uint64_t)p.d->N * (uint64_t)p.tiles;
 }
 
+// Release of dead nets: where each arena region of a round's pieces goes.
+// Regions are numbered piece by piece, the design's regions in order.
+struct RegionPlan {
+    std::vector<size_t> piece_base;          // first region of each piece
+    std::vector<uint64_t> off, slice;        // per region: first word, words per stripe
+    std::vector<uint32_t> stripes;
+    uint64_t peak = 0;                       // arena words the placement needs
+    size_t counters = 0;                     // u64 stripe counters of all regions
+};
+
+constexpr uint32_t kRegionStripes = 16;
+
+// Words to set aside for region r of a piece: the inputs' toggles exactly;
+// for gate outputs the region's learned density (else the design's, else 2
+// transitions per (net, cycle)) with 15% to spare, times the region's growth
+// factor.  Stripes get 1,024 words more each for the uneven spread of
+// reservations over them (plan_regions).
+uint64_t region_words(const Piece &p, int32_t r)
+{
+    const Design *d = p.d;
+    const int64_t nets = d->region_nets[r];
+    if (nets == 0) return 0;
+    double w;
+    if (r == 0) {
+        w = (double)(p.s->tog_prefix[p.c0 + p.cycles] - p.s->tog_prefix[p.c0]);
+    } else {
+        double wpp = d->region_wpp[r] > 0 ? d->region_wpp[r] : d->words_per_ps;
+        if (wpp <= 0) wpp = 2.0 / (double)p.s->period;
+        w = wpp * (double)nets * (double)p.cycles * (double)p.s->period;
+    }
+    return (uint64_t)(w * 1.15 * d->region_grow[r]) + 1;
+}
+
+gs_status region_alloc(gs_ctx *ctx, void **p, size_t bytes)
+{
+    if (ctx->noalloc || hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return gs_fail(ctx, GS_E_NOMEM, "cannot allocate the arena regions' table and counters");
+    }
+    return GS_OK;
+}
+
+// Places the regions first fit over the level steps: a region is taken
+// before the first level that writes into it (the expansion, for the
+// inputs) and given back once the last level that reads it has run.
+void plan_regions(const std::vector<Piece> &ps, RegionPlan &pl)
+{
+    struct Item {
+        int32_t first, last;
+        size_t k;
+    };
+    pl = RegionPlan();
+    std::vector<Item> items;
+    for (const Piece &p : ps) {
+        pl.piece_base.push_back(pl.off.size());
+        for (int32_t r = 0; r < (int32_t)p.d->region_nets.size(); r++) {
+            const uint64_t est = region_words(p, r);
+            uint32_t stripes = 1;
+            while (stripes < kRegionStripes && est / (2ull * stripes) >= 4096) stripes *= 2;
+            const uint64_t slice = ((est + stripes - 1) / stripes + 1024 + 63) & ~63ull;
+            pl.off.push_back(0);
+            pl.slice.push_back(est ? slice : 0);
+            pl.stripes.push_back(stripes);
+            if (est) items.push_back({p.d->region_first[r], p.d->region_last[r], pl.off.size() - 1});
+        }
+    }
+    pl.counters = pl.off.size() * kRegionStripes * kBumpStride;
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.first < b.first; });
+    std::vector<std::pair<uint64_t, uint64_t>> gaps;        // free (first word, words), by address
+    std::vector<Item> live;
+    uint64_t top = 0;
+    for (const Item &it : items) {
+        for (size_t i = 0; i < live.size();) {
+            if (live[i].last < it.first) {
+                gaps.push_back({pl.off[live[i].k], pl.slice[live[i].k] * pl.stripes[live[i].k]});
+                live[i] = live.back();
+                live.pop_back();
+            } else {
+                i++;
+            }
+        }
+        std::sort(gaps.begin(), gaps.end());
+        std::vector<std::pair<uint64_t, uint64_t>> merged;
+        for (const auto &g : gaps) {
+            if (!merged.empty() && merged.back().first + merged.back().second == g.first) merged.back().second += g.second;
+            else merged.push_back(g);
+        }
+        if (!merged.empty() && merged.back().first + merged.back().second == top) {
+            top = merged.back().first;
+            merged.pop_back();
+        }
+        gaps.swap(merged);
+        const uint64_t n = pl.slice[it.k] * pl.stripes[it.k];
+        size_t f = 0;
+        while (f < gaps.size() && gaps[f].second < n) f++;
+        if (f < gaps.size()) {
+            pl.off[it.k] = gaps[f].first;
+            gaps[f].first += n;
+            gaps[f].second -= n;
+            if (gaps[f].second == 0) gaps.erase(gaps.begin() + (long)f);
+        } else {
+            pl.off[it.k] = top;
+            top += n;
+        }
+        pl.peak = std::max(pl.peak, top);
+        live.push_back(it);
+    }
+}
+
 // Builds the segment tables of every level step of a round: step l holds one
 // segment per piece whose design has at least l levels.
 void build_steps(gs_ctx *ctx, const std::vector<Piece> &pieces, const std::vector<WinView> &views, const Tuning &tu,
@@ -138,11 +248,12 @@ gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pi
                        const std::vector<Design *> &designs, const Seg *d_segs, const std::vector<size_t> &step_off,
                        const std::vector<size_t> &step_n, const std::vector<uint64_t> &step_waves,
                        const std::vector<int32_t> &step_kmax, const std::vector<int32_t> &step_wires, const Tuning &tu,
-                       bool commit, bool timing)
+                       bool commit, bool timing, uint64_t region_counters)
 {
     size_t ev = 0;
     HIPCHK(launch_fill_u64(ctx->d_misc, 4, 0ull, hs));
     HIPCHK(launch_fill_u64(ctx->d_bump, (uint64_t)kMaxStripes * kBumpStride, 0ull, hs));
+    if (region_counters) HIPCHK(launch_fill_u64(ctx->d_rbump, region_counters, 0ull, hs));
     for (Design *d : designs) HIPCHK(launch_fill_u64(d->d_stage, kSaifArrays * (uint64_t)d->N, 0ull, hs));
     if (timing) HIPCHK(hipEventRecord(gs_event(ctx, ev++), hs));
     for (size_t i = 0; i < pieces.size(); i++) {
@@ -168,7 +279,7 @@ gs_status record_round(gs_ctx *ctx, hipStream_t hs, const std::vector<Piece> &pi
 // Runs one round.  Window buffers must hold every piece's chunks and
 // arena_words of transitions.
 gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_words, const Tuning &tu, bool commit,
-                    bool timing, RoundResult &res)
+                    bool timing, RoundResult &res, const RegionPlan *plan = nullptr)
 {
     hipStream_t hs = ctx->stream;
     res = RoundResult();
@@ -181,6 +292,34 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     if (st) return st;
     std::vector<WinView> views;
     for (const Piece &p : pieces) views.push_back(gs_make_view(ctx, ctx->win, p.cycles, p.s->period, p.chunk_base, chunks_of(p)));
+    if (plan) {
+        // the region table and the regions' stripe counters
+        const size_t nr = plan->off.size();
+        if (ctx->regions_cap < nr) {
+            gs_dev_free(ctx->d_regions);
+            ctx->d_regions = nullptr;
+            ctx->regions_cap = 0;
+            void *p;
+            if ((st = region_alloc(ctx, &p, sizeof(ArenaRegion) * nr))) return st;
+            ctx->d_regions = (ArenaRegion *)p;
+            ctx->regions_cap = nr;
+        }
+        if (ctx->rbump_cap < plan->counters) {
+            gs_dev_free(ctx->d_rbump);
+            ctx->d_rbump = nullptr;
+            ctx->rbump_cap = 0;
+            void *p;
+            if ((st = region_alloc(ctx, &p, sizeof(unsigned long long) * plan->counters))) return st;
+            ctx->d_rbump = (unsigned long long *)p;
+            ctx->rbump_cap = plan->counters;
+        }
+        std::vector<ArenaRegion> tab(nr);
+        for (size_t k = 0; k < nr; k++)
+            tab[k] = ArenaRegion{plan->off[k], plan->slice[k], ctx->d_rbump + k * kRegionStripes * kBumpStride,
+                                 plan->stripes[k] - 1, 0};
+        HIPCHK(hipMemcpyAsync(ctx->d_regions, tab.data(), sizeof(ArenaRegion) * nr, hipMemcpyHostToDevice, hs));
+        for (size_t i = 0; i < pieces.size(); i++) views[i].regions = ctx->d_regions + plan->piece_base[i];
+    }
     std::vector<Design *> designs;
     for (const Piece &p : pieces)
         if (std::find(designs.begin(), designs.end(), p.d) == designs.end()) designs.push_back(p.d);
@@ -213,7 +352,7 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
             HIPCHK(hipMemcpyAsync(ctx->d_segs, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice, hs));
         HIPCHK(hipMemcpyAsync(ctx->d_c0, c0s.data(), sizeof(int32_t) * c0s.size(), hipMemcpyHostToDevice, hs));
         if ((st = record_round(ctx, hs, pieces, views, designs, ctx->d_segs, step_off, step_n, step_waves, step_kmax,
-                               step_wires, tu, commit, timing)))
+                               step_wires, tu, commit, timing, plan ? plan->counters : 0)))
             return st;
     } else {
         // graph key: everything the recorded launches depend on except the first cycles
@@ -222,6 +361,8 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
         add((uint64_t)(uintptr_t)ctx->win.hdr); add((uint64_t)(uintptr_t)ctx->win.ends);
         add((uint64_t)(uintptr_t)ctx->win.times); add(ctx->win.words); add((uint64_t)(uintptr_t)ctx->d_c0);
         add((uint64_t)tu.cap); add((uint64_t)tu.wpb); add((uint64_t)tu.tpw); add(commit);
+        add(plan ? (uint64_t)(uintptr_t)ctx->d_regions : 0); add(plan ? (uint64_t)(uintptr_t)ctx->d_rbump : 0);
+        add(plan ? (uint64_t)plan->counters : 0);
         for (const Piece &p : pieces) {
             add((uint64_t)p.di); add((uint64_t)p.si); add((uint64_t)p.cycles); add(p.d->version);
         }
@@ -239,7 +380,8 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
             gs_status rs = record_round(ctx, ctx->cap_stream, pieces, views, designs, ge.segs, step_off, step_n,
-                                        step_waves, step_kmax, step_wires, tu, commit, false);
+                                        step_waves, step_kmax, step_wires, tu, commit, false,
+                                        plan ? plan->counters : 0);
             hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
             if (rs) {
                 if (g) (void)hipGraphDestroy(g);
@@ -293,6 +435,28 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     // words handed out: each stripe's counter less the words of its failed tries
     for (uint32_t i = 0; i <= v0.stripe_mask; i++)
         used += std::min<uint64_t>(hb[(size_t)i * kBumpStride] - hb[(size_t)i * kBumpStride + 1], v0.slice_words);
+    std::vector<uint64_t> rused, rfailed;                   // per region (dead nets released)
+    if (plan) {
+        std::vector<unsigned long long> rb(plan->counters);
+        HIPCHK(hipMemcpyAsync(rb.data(), ctx->d_rbump, sizeof(unsigned long long) * rb.size(), hipMemcpyDeviceToHost, hs));
+        HIPCHK(hipStreamSynchronize(hs));
+        const size_t nr = plan->off.size();
+        rused.assign(nr, 0);
+        rfailed.assign(nr, 0);
+        for (size_t k = 0; k < nr; k++)
+            for (uint32_t i = 0; i < plan->stripes[k]; i++) {
+                const size_t c = (k * kRegionStripes + i) * kBumpStride;
+                rused[k] += std::min<uint64_t>(rb[c] - rb[c + 1], plan->slice[k]);
+                rfailed[k] += rb[c + 1];
+            }
+        used = 0;
+        for (uint64_t u : rused) used += u;
+        ctx->stats.release_peak_words = (int64_t)plan->peak;
+        // a region that filled up gets twice the room in the next try
+        for (size_t i = 0; i < pieces.size(); i++)
+            for (size_t r = 0; r < pieces[i].d->region_nets.size(); r++)
+                if (rfailed[plan->piece_base[i] + r]) pieces[i].d->region_grow[r] *= 2.0;
+    }
     ctx->stats.arena_words = (int64_t)used;
     ctx->stats.spilled_lanes += f32[2];
     ctx->stats.unstaged_groups += f32[4];
@@ -315,16 +479,29 @@ gs_status run_round(gs_ctx *ctx, std::vector<Piece> &pieces, uint64_t arena_word
     // learn the design's list density from rounds of one design
     double lane_ps = 0;
     for (const Piece &p : pieces) lane_ps += (double)p.cycles * (double)p.s->period;
-    if (designs.size() == 1 && lane_ps > 0)
-        designs[0]->words_per_ps = (double)used / ((double)std::max(1, designs[0]->N) * lane_ps);
+    if (designs.size() == 1 && lane_ps > 0) {
+        Design *d = designs[0];
+        d->words_per_ps = (double)used / ((double)std::max(1, d->N) * lane_ps);
+        if (plan)                                           // and each region's
+            for (size_t r = 1; r < d->region_nets.size(); r++) {
+                if (!d->region_nets[r]) continue;
+                uint64_t u = 0;
+                for (size_t i = 0; i < pieces.size(); i++) u += rused[plan->piece_base[i] + r];
+                d->region_wpp[r] = (double)u / ((double)d->region_nets[r] * lane_ps);
+                d->region_grow[r] = 1.0;                    // the measured density replaces an earlier growth
+            }
+    }
     ctx->stats.gate_eval_ms += res.gate_eval_ms;
     ctx->stats.expand_ms += res.expand_ms;
     ctx->stats.gate_eval_launches += res.launches;
     ctx->stats.windows += (int64_t)pieces.size();
     for (const Piece &p : pieces) ctx->stats.gate_cycles += (int64_t)p.d->G * p.cycles;
-    // the round's windows stay readable through gs_read_waveform
+    // the round's windows stay readable through gs_read_waveform (not when
+    // the space of dead nets was reused)
     ctx->last.clear();
+    ctx->last_released = plan != nullptr;
     for (const Piece &p : pieces) {
+        if (plan) break;
         LastWindow lw;
         lw.design = p.di;
         lw.stim = p.si;
@@ -399,11 +576,42 @@ gs_status run_pieces(gs_ctx *ctx, std::vector<Piece> pending, const Tuning &tu, 
         }
         const uint64_t max_words = (ctx->budget - hdr) / sizeof(int32_t);
         uint64_t words = std::min(max_words, std::max(std::max(guess, min_words), std::max(grown, ctx->win.words)));
+        // dead nets released: the arena is what the regions' placement needs
+        RegionPlan plan;
+        if (ctx->releasing) {
+            plan_regions(round, plan);
+            if (plan.peak > max_words) {
+                if (round.size() > 1) {
+                    max_round = round.size() / 2;
+                    for (auto it = round.rbegin(); it != round.rend(); ++it) pending.push_back(*it);
+                    continue;
+                }
+                const int32_t a_cycles = split_cycles(round[0]);
+                if (a_cycles <= 0)
+                    return gs_fail(ctx, GS_E_NOMEM, "the arena regions of one %d-cycle window exceed the memory budget",
+                                   round[0].cycles);
+                Piece p = round[0], a = p, b = p;
+                a.cycles = a_cycles;
+                a.tiles = (a.cycles + kLanes - 1) / kLanes;
+                b.c0 = p.c0 + a.cycles;
+                b.cycles = p.cycles - a.cycles;
+                b.tiles = (b.cycles + kLanes - 1) / kLanes;
+                pending.push_back(b);
+                pending.push_back(a);
+                continue;
+            }
+            words = std::max<uint64_t>(plan.peak, std::min(max_words, ctx->win.words));
+        }
         RoundResult rr;
-        gs_status st = run_round(ctx, round, words, tu, commit, timing, rr);
+        gs_status st = run_round(ctx, round, words, tu, commit, timing, rr, ctx->releasing ? &plan : nullptr);
         if (st) return st;
         if (gate_eval_ms) *gate_eval_ms += rr.gate_eval_ms;
         if (!rr.retry) continue;
+        if (ctx->releasing) {
+            // the regions that filled up were given twice the room: plan again
+            for (auto it = round.rbegin(); it != round.rend(); ++it) pending.push_back(*it);
+            continue;
+        }
         // arena full: grow, else split the round, else halve the single window
         if (words < max_words) {
             grown = std::min(max_words, words * 2);
@@ -504,6 +712,7 @@ extern "C" gs_status gs_cycle_profile(gs_ctx *ctx, int32_t design, int32_t stim,
     gs_status st = check_job(ctx, design, stim, cycle_begin, cycle_end);
     if (st) return st;
     if (ctx->stims[stim]->carry) return gs_fail(ctx, GS_E_INVALID, "no cycle profile of a continuous view");
+    if (ctx->opt.release_dead) return gs_fail(ctx, GS_E_INVALID, "no cycle profile when dead nets are released");
     const int32_t n = cycle_end - cycle_begin;
     (void)hipSetDevice(ctx->opt.device);
     const Design *d = ctx->designs[design];
@@ -575,7 +784,15 @@ extern "C" gs_status gs_simulate(gs_ctx *ctx, int32_t design, int32_t stim, int3
     (void)hipSetDevice(ctx->opt.device);
     const uint64_t t_start = gs_now_ns();
     ctx->last.clear();
+    ctx->last_released = false;
     Design *d = ctx->designs[design];
+    // release of dead nets applies to this call only (batches, the
+    // allocation-free call and serving keep every net)
+    struct Releasing {
+        gs_ctx *c;
+        ~Releasing() { c->releasing = false; }
+    } releasing_guard{ctx};
+    ctx->releasing = ctx->opt.release_dead != 0;
     // a design's first run learns its transition density from a 64-cycle
     // pilot (nothing committed), so that the arena of the real windows is
     // sized from it rather than guessed and retried

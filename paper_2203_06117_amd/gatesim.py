@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("window_cycles", C.c_int32),
                 ("lds_cap", C.c_int32), ("waves_per_block", C.c_int32), ("schedule", C.c_int32),
                 ("timing", C.c_int32), ("tiles_per_wave", C.c_int32), ("autotune", C.c_int32),
-                ("wire_transport", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("wire_transport", C.c_int32), ("release_dead", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class DesignInfo(C.Structure):
@@ -57,7 +57,7 @@ class Stats(C.Structure):
                 ("gate_eval_launches", C.c_int64), ("windows", C.c_int64), ("window_retries", C.c_int64),
                 ("gate_cycles", C.c_int64), ("spilled_lanes", C.c_int64), ("arena_words", C.c_int64),
                 ("graph_launches", C.c_int64), ("unstaged_groups", C.c_int64), ("queue_overflows", C.c_int64),
-                ("reserved", C.c_int64 * 3)]
+                ("release_peak_words", C.c_int64), ("reserved", C.c_int64 * 2)]
 
 
 class Tuning(C.Structure):
@@ -189,7 +189,7 @@ class GateSim:
     def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0, arena=None,
                  window_cycles: int = 0, lds_cap: int = 0, waves_per_block: int = 4,
                  schedule: int = SCHED_LEVELS, timing: bool = False, tiles_per_wave: int = 0,
-                 autotune: bool = False, wire_transport: bool = False):
+                 autotune: bool = False, wire_transport: bool = False, release_dead: bool = False):
         o = Options()
         _lib.gs_default_options(C.byref(o))
         o.device = device
@@ -207,6 +207,7 @@ class GateSim:
         o.tiles_per_wave = tiles_per_wave
         o.autotune = 1 if autotune else 0
         o.wire_transport = 1 if wire_transport else 0
+        o.release_dead = 1 if release_dead else 0
         h = P()
         st = _lib.gs_create(C.byref(o), C.byref(h))
         if st != GS_OK:
