@@ -19,7 +19,8 @@ Also reported (one JSON line):
                 one process per host core, and single-threaded (whose SAIF
                 also re-checks the GPU result)
   glitchy       the 8M-gate glitch-heavy workload: first call and steady
-                state, with its compulsory-bytes roofline
+                state, with its compulsory-bytes roofline, and again with
+                dead nets released (the arena's peak against the words stored)
   batched       64 uneven instances (1e4-5e5 gates, 200-5000 cycles) run as
                 one batch (autotuned, replayed from a captured HIP graph):
                 aggregate gate-cycles/s beside the same jobs run one by one,
@@ -408,6 +409,7 @@ def run_glitchy(args, torch, synth, GateSim):
         ok = bool(all(np.array_equal(a, ref[k]) for a, k in zip(g, ("tc", "t0", "t1"))))
         log(f"glitchy: oracle cycle 0 in {time.perf_counter() - tq:.1f}s, parity {ok}")
     sim.close()
+    release = run_glitchy_release(torch, w, GateSim, tc, ig) if args.release_leg else None
     return {"workload": "glitchy-8M", "gates": Gn, "inputs": net["n_inputs"], "levels": 200, "cycles": C,
             "period_ps": stim["period"], "toggle_p": 0.3, "delays_ps": "3-120",
             "value": round(Gn * C * steps / elapsed, 1), "unit": "gate-cycles/s",
@@ -425,7 +427,41 @@ def run_glitchy(args, torch, synth, GateSim):
                          "unit": "GB/s", "frac": round(b_min * gc_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
                          "b_min_bytes_per_gate_cycle": round(b_min, 3), "avg_launch_us": round(avg_s * 1e6, 2),
                          "launches": launches},
-            "oracle_cycle0_ok": ok}
+            "oracle_cycle0_ok": ok, "release_dead": release}
+
+
+def run_glitchy_release(torch, w, GateSim, tc_ref, ig_ref):
+    """The glitch-heavy workload with dead nets released: the arena words
+    the regions take at their peak against the transitions the window
+    stores, the first call and one steady step, and the SAIF compared with
+    the run that keeps every net."""
+    net, stim = w["netlist"], w["stimulus"]
+    Gn, C = net["n_gates"], stim["n_cycles"]
+    sim = GateSim(device=0, stream=torch.cuda.current_stream(), timing=True, release_dead=True)
+    d, s = sim.load_work(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.simulate(d, s, 0, C)
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    st_first = sim.stats(reset=True)
+    sim.read_saif(d, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.simulate(d, s, 0, C)
+    tc, _, _, ig = sim.read_saif_ig(d, reset=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    same = bool(np.array_equal(tc, tc_ref) and np.array_equal(ig, ig_ref))
+    peak, stored = st["release_peak_words"], st["arena_words"]
+    log(f"glitchy with release: peak {peak} of {stored} stored words ({peak / max(1, stored):.3f}), first call "
+        f"{first_s:.2f}s ({st_first['window_retries']} retries), step {elapsed * 1e3:.1f} ms, same SAIF {same}")
+    return {"peak_arena_words": peak, "stored_words": stored, "peak_over_stored": round(peak / max(1, stored), 4),
+            "first_call_s": round(first_s, 2), "first_call_window_retries": st_first["window_retries"],
+            "window_retries": st["window_retries"], "ms_per_step": round(elapsed * 1e3, 1),
+            "value": round(Gn * C / elapsed, 1), "unit": "gate-cycles/s", "same_saif_as_keeping_every_net": same}
 
 
 def run_batch(args, torch, synth, G):
@@ -730,6 +766,8 @@ def main():
     ap.add_argument("--wpb", type=int, default=4)
     ap.add_argument("--cpu-cycles", type=int, default=30, help="oracle sample: first N cycles (0 = skip)")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--no-release-leg", dest="release_leg", action="store_false",
+                    help="skip the glitch-heavy run with dead nets released")
     ap.add_argument("--no-window-leg", dest="window_leg", action="store_false",
                     help="skip the 1,000-cycle-window figure of the scale leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

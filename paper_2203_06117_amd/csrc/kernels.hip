@@ -1673,8 +1673,11 @@ __global__ __launch_bounds__(512) void gate_eval_kernel(const Seg *__restrict__ 
     // and need not be reloaded after the kernel's own stores
     const Seg sg = *kons(segs + si);
     // a round whose arena or a chunk already overflowed is rerun or failed
-    // as a whole: its remaining waves skip their work
-    if ((*kons(sg.win.flags) | *kons(sg.win.flags + 1)) != 0u) return;
+    // as a whole: its remaining waves skip their work.  With arena regions
+    // (dead nets released) a full region does not stop the round, so that
+    // every region that is too small shows up in one try (a chunk that got
+    // no space is written empty, which later reads take as no edges).
+    if (((sg.win.regions ? 0u : *kons(sg.win.flags)) | *kons(sg.win.flags + 1)) != 0u) return;
     const uint32_t local = (uint32_t)(w - sg.wave_begin);
     const uint32_t ntile = (uint32_t)sg.win.n_tiles;
     const uint32_t ngroup = (ntile + tpw - 1) / tpw;
