@@ -302,24 +302,39 @@ hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n
 // --------------------------------------------------------------------------
 constexpr uint32_t kStripeTries = 16;
 
-__device__ __forceinline__ uint64_t arena_reserve(const WinView &win, uint32_t stripe0, uint32_t n, int lane)
+// `pick` selects the first stripe (masked to the stripes there are); with
+// dead nets released the reservation comes from region `region` of the
+// window's table, whose entry is read here, at the reservation, so that its
+// fields hold no registers through the rest of the wave's work.
+__device__ __forceinline__ uint64_t arena_reserve(const WinView &win, uint32_t region, uint32_t pick, uint32_t n,
+                                                  int lane)
 {
-    uint32_t s = stripe0;
+    unsigned long long *bump = win.bump;
+    uint64_t slice = win.slice_words, off = win.arena_off;
+    uint32_t mask = win.stripe_mask;
+    if (win.regions) {
+        const ArenaRegion r = *kons(win.regions + region);
+        bump = r.bump;
+        slice = r.slice_words;
+        off = r.off;
+        mask = r.stripe_mask;
+    }
+    uint32_t s = pick & mask;
     // the first try inline; the rare further tries in a loop kept rolled,
     // so that the common path carries no extra registers
 #pragma nounroll
     for (uint32_t k = 0; k < kStripeTries; k++) {
         uint64_t b = 0;
         if (lane == 0)
-            b = __hip_atomic_fetch_add(glob(win.bump + (size_t)s * kBumpStride), (unsigned long long)n,
+            b = __hip_atomic_fetch_add(glob(bump + (size_t)s * kBumpStride), (unsigned long long)n,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         b = uniform64(b);
-        if (b + n <= win.slice_words) return win.arena_off + (uint64_t)s * win.slice_words + b;
+        if (b + n <= slice) return off + (uint64_t)s * slice + b;
         if (lane == 0)
-            __hip_atomic_fetch_add(glob(win.bump + (size_t)s * kBumpStride + 1), (unsigned long long)n,
+            __hip_atomic_fetch_add(glob(bump + (size_t)s * kBumpStride + 1), (unsigned long long)n,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (win.stripe_mask == 0) break;
-        s = (s + 97u) & win.stripe_mask;
+        if (mask == 0) break;
+        s = (s + 97u) & mask;
     }
     if (lane == 0) __hip_atomic_fetch_or(glob(win.flags), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return ~0ull;
@@ -371,13 +386,6 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
 {
     extern __shared__ uint32_t ex_hist[];                   // kExpandGroup * 64 counters per wave
     const int32_t cycle0 = *glob(cycle0_p);
-    if (win.regions) {                                      // region 0 holds the inputs (dead nets released)
-        const ArenaRegion r = *kons(win.regions);
-        win.arena_off = r.off;
-        win.slice_words = r.slice_words;
-        win.bump = r.bump;
-        win.stripe_mask = r.stripe_mask;
-    }
     const int lane = threadIdx.x & (kLanes - 1);
     const uint32_t wib = uniform(threadIdx.x / kLanes);
     const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kLanes) + wib;
@@ -407,11 +415,10 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     // one arena reservation for the group's chunks
-    const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
     uint64_t base = 0;
     bool ok = true;
     if (n > 0) {
-        base = arena_reserve(win, stripe, n, lane);
+        base = arena_reserve(win, 0, blockIdx.x + salt, n, lane);     // region 0: the inputs
         ok = base != ~0ull;
     }
     // toggles, one per lane and row: cycle index (group-relative), local time,
@@ -942,7 +949,7 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
                                               uint32_t tile_g, uint32_t ng, int lane, uint32_t lut_base,
                                               uint32_t out_base, uint32_t c_pos, const uint32_t (&ev)[K][GT / 2],
                                               uint32_t salt, bool transport, uint32_t &tc_sum, uint32_t &ig_sum,
-                                              uint32_t &nact_sum, int32_t &t1_lane)
+                                              uint32_t &nact_sum, int32_t &t1_lane, uint32_t region)
 {
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;
@@ -1081,11 +1088,10 @@ __device__ __forceinline__ bool compact_group(const WinView &win, const Arcs<K> 
     tc_sum += R;
 
     // one reservation for the group's output chunks, exactly their words
-    const uint32_t stripe = (blockIdx.x + salt) & win.stripe_mask;
     uint64_t wbase = 0;
     bool ok = true;
     if (R > 0) {
-        wbase = arena_reserve(win, stripe, R, lane);
+        wbase = arena_reserve(win, region, blockIdx.x + salt, R, lane);
         ok = wbase != ~0ull;
         if (!ok) wbase = 0;
     }
@@ -1169,14 +1175,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
 {
     static_assert(!(CONT && (WIRES || REMAP)), "continuous segments: designs without interconnect delays, whole windows");
     constexpr uint32_t GT = K <= 3 ? 4 : 2;
-    WinView win = sg.win;
-    if (win.regions) {                          // the output's region of the arena (dead nets released)
-        const ArenaRegion r = *kons(win.regions + g.dead);
-        win.arena_off = r.off;
-        win.slice_words = r.slice_words;
-        win.bump = r.bump;
-        win.stripe_mask = r.stripe_mask;
-    }
+    const WinView &win = sg.win;
     const bool transport = (sg.mode & 1u) != 0;
     const int32_t T = win.period;
     const uint32_t ntile = (uint32_t)win.n_tiles;
@@ -1260,7 +1259,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         const uint32_t c_incl = wave_incl_scan(c_tot);
         const uint32_t bound = (uint32_t)lane63(c_incl);
         const uint32_t c_pos = stage_base + wave_shr1(c_incl);  // chunk's first word in the LDS stage
-        const uint32_t stripe = (blockIdx.x + sg.salt) & win.stripe_mask;
+        const uint32_t pick = blockIdx.x + sg.salt;           // the arena stripe (see arena_reserve)
         const bool staged = bound <= kStageWords;
         // staged groups of gates with up to three pins take the compacted
         // path, which reserves exactly its output words later
@@ -1321,7 +1320,8 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         if constexpr (K <= 3) {
             if (try_compact) {
                 if (compact_group<K, WIRES, GT>(win, arc, g.truth, out_row, tile0 + gb, ng, lane, lut_base, out_base,
-                                                c_pos, ev, sg.salt, transport, tc_sum, ig_sum, nact_sum, t1_lane))
+                                                c_pos, ev, sg.salt, transport, tc_sum, ig_sum, nact_sum, t1_lane,
+                                                g.dead))
                     continue;
                 // too many lanes with two or more events: the per-tile walk
                 if (lane == 0)
@@ -1341,7 +1341,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
         bool gok = true;
         uint32_t used = 0;                                      // staged: its words handed out
         if (staged && obound > 0) {
-            gbase = arena_reserve(win, stripe, obound, lane);
+            gbase = arena_reserve(win, g.dead, pick, obound, lane);
             gok = gbase != ~0ull;
         }
         for (uint32_t u = 0; u < ng; u++) {
@@ -1529,7 +1529,7 @@ __device__ __forceinline__ void eval_gate(const Seg &sg, const GateRec &g, uint3
                 obase = ok ? gbase + used : 0;
                 if (ok) used += total;
             } else if (ok && total > 0) {
-                obase = arena_reserve(win, stripe, total, lane);
+                obase = arena_reserve(win, g.dead, pick, total, lane);
                 ok = obase != ~0ull;
                 if (!ok) obase = 0;
             }
