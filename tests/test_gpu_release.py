@@ -122,3 +122,24 @@ def test_release_fits_where_every_net_does_not(G):
     ref = oracle.simulate(w)
     got = run(G, w, hbm_budget=budget, release_dead=True)
     assert_same(got, ref, "tight budget")
+
+
+def test_release_with_continuous_views_and_graphs(G):
+    """Release combined with a cycle-parallel continuous view (carried
+    edges), with captured-graph rounds replayed for several windows, and
+    with transport wires."""
+    w = synth.small_random(9960, 900, 20, 24, 16 * 24, 150, 0.35, 2, 50, cond_frac=0.2, extra=1, extra_p=0.3,
+                           skew=50, edge_frac=0.2)
+    with G.GateSim(release_dead=True, window_cycles=64) as sim:
+        d, s = sim.load_work(w)
+        v = sim.continuous_stimulus(s, 16)
+        sim.simulate(d, v, 0, 24)
+        tc, t0, t1, ig = sim.read_saif_ig(d)
+    assert_same({"tc": tc, "t0": t0, "t1": t1, "ig": ig}, oracle.simulate(w, segment_cycles=16), "continuous")
+    ref = oracle.simulate(w)
+    got = run(G, w, release_dead=True, window_cycles=64, schedule=G.SCHED_GRAPH)
+    assert_same(got, ref, "graphs")
+    assert got["stats"]["graph_launches"] > 0
+    wt = synth.small_random(9961, 700, 20, 20, 200, 300, 0.4, 1, 40, wire=(1, 20), extra=3, extra_p=0.5, skew=50)
+    wt["net_filter"] = False
+    assert_same(run(G, wt, release_dead=True, wire_transport=True), oracle.simulate(wt), "transport wires")
