@@ -388,17 +388,58 @@ static gs_status levelize(gs_ctx *ctx, Design *d)
     HIPCHK(hipMemcpyAsync(d->d_fanin_ptr, d->fanin_ptr.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
     if (d->F) HIPCHK(hipMemcpyAsync(d->d_fanin_net, d->fanin_net.data(), sizeof(int32_t) * d->F, hipMemcpyHostToDevice, s));
     HIPCHK(launch_level_init(d->d_level, I, G, s));
-    unsigned int *cnt = (unsigned int *)(ctx->d_misc + 4);
-    unsigned int h[2];
     int iters = 0;
-    for (;;) {
-        HIPCHK(launch_fill_u32(cnt, 2, 0u, s));
-        HIPCHK(launch_level_step(d->d_fanin_ptr, d->d_fanin_net, d->d_level, I, G, cnt, s));
-        HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    if (G) {
+        // temporary buffers of the frontier levelizer, freed on return
+        struct Temp {
+            std::vector<void *> v;
+            ~Temp() { for (void *q : v) gs_dev_free(q); }
+        } tmp;
+        auto take = [&](size_t bytes, void **q) {
+            gs_status r = dev_alloc(ctx, q, std::max<size_t>(bytes, 8));
+            if (!r) tmp.v.push_back(*q);
+            return r;
+        };
+        void *pp[7];
+        if ((st = take(sizeof(unsigned int) * G, &pp[0])) || (st = take(sizeof(unsigned int) * G, &pp[1])) ||
+            (st = take(sizeof(int64_t) * ((size_t)G + 1), &pp[2])) || (st = take(sizeof(int32_t) * (size_t)d->F, &pp[3])) ||
+            (st = take(sizeof(int32_t) * G, &pp[4])) || (st = take(sizeof(int32_t) * G, &pp[5])) ||
+            (st = take(sizeof(unsigned int) * 2, &pp[6])))
+            return st;
+        unsigned int *pending = (unsigned int *)pp[0], *fo_cnt = (unsigned int *)pp[1], *sizes = (unsigned int *)pp[6];
+        int64_t *fo_ptr = (int64_t *)pp[2];
+        int32_t *fo = (int32_t *)pp[3], *cur = (int32_t *)pp[4], *nxt = (int32_t *)pp[5];
+        // sink lists of the gate outputs: counts, their prefix sum on the host, fill
+        HIPCHK(launch_fill_u32(fo_cnt, (uint64_t)G, 0u, s));
+        HIPCHK(launch_fanout_count(d->d_fanin_ptr, d->d_fanin_net, I, G, pending, fo_cnt, s));
+        std::vector<unsigned int> hc(G);
+        HIPCHK(hipMemcpyAsync(hc.data(), fo_cnt, sizeof(unsigned int) * G, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        iters++;
-        if (h[1] == 0) break;
-        if (h[0] == 0) return gs_fail(ctx, GS_E_NOT_DAG, "netlist has a combinational cycle (%u gates unplaced)", h[1]);
+        std::vector<int64_t> hp((size_t)G + 1, 0);
+        for (int32_t g = 0; g < G; g++) hp[g + 1] = hp[g] + hc[g];
+        HIPCHK(hipMemcpyAsync(fo_ptr, hp.data(), sizeof(int64_t) * ((size_t)G + 1), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_fill_u32(fo_cnt, (uint64_t)G, 0u, s));
+        HIPCHK(launch_fanout_fill(d->d_fanin_ptr, d->d_fanin_net, I, G, fo_ptr, fo_cnt, fo, s));
+        // frontiers, one level each
+        unsigned int n = 0;
+        HIPCHK(launch_fill_u32(sizes, 2, 0u, s));
+        HIPCHK(launch_level_seed(pending, d->d_level, I, G, cur, sizes, s));
+        HIPCHK(hipMemcpyAsync(&n, sizes, sizeof(n), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int64_t placed = n;
+        while (n > 0) {
+            iters++;
+            HIPCHK(launch_fill_u32(sizes + 1, 1, 0u, s));
+            HIPCHK(launch_level_frontier(cur, n, fo_ptr, fo, d->d_fanin_ptr, d->d_fanin_net, pending, d->d_level, I,
+                                         nxt, sizes + 1, s));
+            HIPCHK(hipMemcpyAsync(&n, sizes + 1, sizeof(n), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            placed += n;
+            std::swap(cur, nxt);
+        }
+        if (placed < G)
+            return gs_fail(ctx, GS_E_NOT_DAG, "netlist has a combinational cycle (%lld gates unplaced)",
+                           (long long)(G - placed));
     }
     d->level.resize(G);
     if (G) HIPCHK(hipMemcpyAsync(d->level.data(), d->d_level + I, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));

@@ -190,8 +190,16 @@ hipError_t launch_add_u64_guarded(unsigned long long *dst, const unsigned long l
                                   const unsigned int *flags, hipStream_t s);
 
 hipError_t launch_level_init(int32_t *level, int32_t n_inputs, int32_t n_gates, hipStream_t s);
-hipError_t launch_level_step(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t *level,
-                             int32_t n_inputs, int32_t n_gates, unsigned int *counters, hipStream_t s);
+hipError_t launch_fanout_count(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t n_inputs, int32_t n_gates,
+                               unsigned int *pending, unsigned int *fo_cnt, hipStream_t s);
+hipError_t launch_fanout_fill(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t n_inputs, int32_t n_gates,
+                              const int64_t *fo_ptr, unsigned int *cursor, int32_t *fo, hipStream_t s);
+hipError_t launch_level_seed(const unsigned int *pending, int32_t *level, int32_t n_inputs, int32_t n_gates,
+                             int32_t *frontier, unsigned int *size, hipStream_t s);
+hipError_t launch_level_frontier(const int32_t *frontier, unsigned int n, const int64_t *fo_ptr, const int32_t *fo,
+                                 const int64_t *fanin_ptr, const int32_t *fanin_net, unsigned int *pending,
+                                 int32_t *level, int32_t n_inputs, int32_t *next, unsigned int *next_size,
+                                 hipStream_t s);
 hipError_t launch_level_bucket(const int32_t *level, int32_t n_inputs, int32_t n_gates,
                                unsigned int *cursor, int32_t *perm, int count_only, hipStream_t s);
 

@@ -213,9 +213,12 @@ hipError_t launch_add_u64(unsigned long long *dst, const unsigned long long *src
 // --------------------------------------------------------------------------
 // Levelizer (Section 3: the netlist is partitioned by logic level).  Level 0
 // holds the inputs; a gate's level is 1 + the largest level of its fanin
-// nets.  Relaxation sweeps: a gate takes its level once every fanin has
-// one; a sweep that places nothing while gates remain proves a cycle.
-// counters[0] = gates placed in the sweep, counters[1] = gates still open.
+// nets.  Frontier order: every gate counts its fanins driven by gates
+// (`pending`) and every gate output lists its sink gates (a fanout CSR);
+// the gates without such fanins form level 1, and a frontier's gates
+// release their sinks, a sink joining the next frontier when its last fanin
+// gate has been placed (its level computed then from its fanins' levels).
+// The work is one pass over the fanins; gates never placed sit on a cycle.
 // --------------------------------------------------------------------------
 __global__ void level_init_kernel(int32_t *level, int32_t n_inputs, int32_t n_nets)
 {
@@ -223,31 +226,72 @@ __global__ void level_init_kernel(int32_t *level, int32_t n_inputs, int32_t n_ne
     if (n < n_nets) level[n] = n < n_inputs ? 0 : -1;
 }
 
-__global__ void level_step_kernel(const int64_t *__restrict__ fanin_ptr, const int32_t *__restrict__ fanin_net,
-                                  int32_t *level, int32_t n_inputs, int32_t n_gates, unsigned int *counters)
+// pending[g] = fanins of g driven by gates; fo_cnt[h] += 1 for every such
+// fanin h (a gate output), the size of h's sink list.
+__global__ void fanout_count_kernel(const int64_t *__restrict__ fanin_ptr, const int32_t *__restrict__ fanin_net,
+                                    int32_t n_inputs, int32_t n_gates, unsigned int *pending, unsigned int *fo_cnt)
 {
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    bool placed = false, blocked = false;
-    if (g < n_gates && level[n_inputs + g] < 0) {
-        int32_t mx = 0;
-        for (int64_t s = fanin_ptr[g]; s < fanin_ptr[g + 1]; s++) {
-            const int32_t l = __hip_atomic_load(&level[fanin_net[s]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (l < 0) {
-                blocked = true;
-                break;
-            }
-            mx = l > mx ? l : mx;
-        }
-        if (!blocked) {
-            __hip_atomic_store(&level[n_inputs + g], mx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            placed = true;
+    if (g >= n_gates) return;
+    unsigned int c = 0;
+    for (int64_t s = fanin_ptr[g]; s < fanin_ptr[g + 1]; s++) {
+        const int32_t n = fanin_net[s];
+        if (n >= n_inputs) {
+            atomicAdd(&fo_cnt[n - n_inputs], 1u);
+            c++;
         }
     }
-    // one update of each counter per wave
-    const uint64_t bp = __ballot(placed), bb = __ballot(blocked);
-    if ((threadIdx.x & (kLanes - 1)) == 0) {
-        if (bp) atomicAdd(&counters[0], (unsigned int)__popcll(bp));
-        if (bb) atomicAdd(&counters[1], (unsigned int)__popcll(bb));
+    pending[g] = c;
+}
+
+// Sink lists: fo[fo_ptr[h] ...] = the gates reading gate h's output.
+__global__ void fanout_fill_kernel(const int64_t *__restrict__ fanin_ptr, const int32_t *__restrict__ fanin_net,
+                                   int32_t n_inputs, int32_t n_gates, const int64_t *__restrict__ fo_ptr,
+                                   unsigned int *cursor, int32_t *fo)
+{
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_gates) return;
+    for (int64_t s = fanin_ptr[g]; s < fanin_ptr[g + 1]; s++) {
+        const int32_t n = fanin_net[s];
+        if (n >= n_inputs) {
+            const unsigned int k = atomicAdd(&cursor[n - n_inputs], 1u);
+            fo[fo_ptr[n - n_inputs] + k] = g;
+        }
+    }
+}
+
+// The first frontier: gates fed by inputs only, at level 1.
+__global__ void level_seed_kernel(const unsigned int *__restrict__ pending, int32_t *level, int32_t n_inputs,
+                                  int32_t n_gates, int32_t *frontier, unsigned int *size)
+{
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_gates || pending[g] != 0) return;
+    level[n_inputs + g] = 1;
+    frontier[atomicAdd(size, 1u)] = g;
+}
+
+// One frontier: each of its gates releases its sinks; the sink whose last
+// gate fanin this is takes 1 + the largest level of its fanins (all placed
+// by now) and joins the next frontier.
+__global__ void level_frontier_kernel(const int32_t *__restrict__ frontier, unsigned int n,
+                                      const int64_t *__restrict__ fo_ptr, const int32_t *__restrict__ fo,
+                                      const int64_t *__restrict__ fanin_ptr, const int32_t *__restrict__ fanin_net,
+                                      unsigned int *pending, int32_t *level, int32_t n_inputs, int32_t *next,
+                                      unsigned int *next_size)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g = frontier[i];
+    for (int64_t k = fo_ptr[g]; k < fo_ptr[g + 1]; k++) {
+        const int32_t t = fo[k];
+        if (atomicSub(&pending[t], 1u) != 1u) continue;
+        int32_t mx = 0;
+        for (int64_t s = fanin_ptr[t]; s < fanin_ptr[t + 1]; s++) {
+            const int32_t l = __hip_atomic_load(&level[fanin_net[s]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            mx = l > mx ? l : mx;
+        }
+        __hip_atomic_store(&level[n_inputs + t], mx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        next[atomicAdd(next_size, 1u)] = t;
     }
 }
 
@@ -270,12 +314,41 @@ hipError_t launch_level_init(int32_t *level, int32_t n_inputs, int32_t n_gates, 
     return hipGetLastError();
 }
 
-hipError_t launch_level_step(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t *level,
-                             int32_t n_inputs, int32_t n_gates, unsigned int *counters, hipStream_t s)
+hipError_t launch_fanout_count(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t n_inputs, int32_t n_gates,
+                               unsigned int *pending, unsigned int *fo_cnt, hipStream_t s)
 {
     if (n_gates == 0) return hipSuccess;
-    hipLaunchKernelGGL(level_step_kernel, dim3((n_gates + 255) / 256), dim3(256), 0, s, fanin_ptr, fanin_net,
-                       level, n_inputs, n_gates, counters);
+    hipLaunchKernelGGL(fanout_count_kernel, dim3((n_gates + 255) / 256), dim3(256), 0, s, fanin_ptr, fanin_net,
+                       n_inputs, n_gates, pending, fo_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fanout_fill(const int64_t *fanin_ptr, const int32_t *fanin_net, int32_t n_inputs, int32_t n_gates,
+                              const int64_t *fo_ptr, unsigned int *cursor, int32_t *fo, hipStream_t s)
+{
+    if (n_gates == 0) return hipSuccess;
+    hipLaunchKernelGGL(fanout_fill_kernel, dim3((n_gates + 255) / 256), dim3(256), 0, s, fanin_ptr, fanin_net,
+                       n_inputs, n_gates, fo_ptr, cursor, fo);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_seed(const unsigned int *pending, int32_t *level, int32_t n_inputs, int32_t n_gates,
+                             int32_t *frontier, unsigned int *size, hipStream_t s)
+{
+    if (n_gates == 0) return hipSuccess;
+    hipLaunchKernelGGL(level_seed_kernel, dim3((n_gates + 255) / 256), dim3(256), 0, s, pending, level, n_inputs,
+                       n_gates, frontier, size);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_frontier(const int32_t *frontier, unsigned int n, const int64_t *fo_ptr, const int32_t *fo,
+                                 const int64_t *fanin_ptr, const int32_t *fanin_net, unsigned int *pending,
+                                 int32_t *level, int32_t n_inputs, int32_t *next, unsigned int *next_size,
+                                 hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(level_frontier_kernel, dim3((n + 255) / 256), dim3(256), 0, s, frontier, n, fo_ptr, fo,
+                       fanin_ptr, fanin_net, pending, level, n_inputs, next, next_size);
     return hipGetLastError();
 }
 
