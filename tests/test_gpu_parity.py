@@ -322,6 +322,48 @@ def test_dense_activity(G):
             assert got[4]["spilled_lanes"] > 0
 
 
+def tile_fanin_words(w, ref_probes, n_nets, n_cycles):
+    """Fanin words of every (gate, 64-cycle tile): the transitions of its pin
+    nets over the tile, from the oracle's probe lengths."""
+    ln = np.array([p[2] for p in ref_probes], dtype=np.int64).reshape(n_nets, n_cycles)
+    nt = (n_cycles + 63) // 64
+    per_tile = np.zeros((n_nets, nt), dtype=np.int64)
+    for t in range(nt):
+        per_tile[:, t] = ln[:, t * 64:(t + 1) * 64].sum(1)
+    fp = np.asarray(w["netlist"]["fanin_ptr"])
+    fn = np.asarray(w["netlist"]["fanin_net"])
+    return np.array([per_tile[fn[fp[g]:fp[g + 1]]].sum(0) for g in range(len(fp) - 1)])
+
+
+@pytest.mark.parametrize("wires", [False, True])
+def test_tile_stage_mix(G, wires):
+    """Tile groups too large for the 512-word fanin stage, at the caps that
+    dense designs take: each tile whose fanin fits the stage is staged alone
+    and walked from LDS, each larger one is walked from the arena, in the
+    same group.  The design has tiles of both kinds (up to three times the
+    stage); every tile shape and block shape must match the oracle, with
+    interconnect delays filtered or transported."""
+    w = synth.small_random(79, 500, 16, 10, 192, 2000, 0.9, 2, 60, cond_frac=0.2, extra=5, extra_p=0.8,
+                           edge_frac=0.3, wire=(1, 30) if wires else None)
+    n_nets, C = 16 + 500, 192
+    probes = [(n, c) for n in range(n_nets) for c in range(C)]
+    runs = [("filtered", True)] + ([("transport", False)] if wires else [])
+    for name, flt in runs:
+        w["net_filter"] = flt
+        ref = oracle.Oracle(w["netlist"], w["arcs"], w["wires"]).run(w["stimulus"], probes=probes, probe_cap=1,
+                                                                       net_filter=flt)
+        fw = tile_fanin_words(w, ref["probes"], n_nets, C)
+        classes = ((fw <= 512).sum(), (fw > 512).sum(), (fw > 1024).sum())
+        say("tile stage", name, "tiles by fanin words (<=512, >512, >1024):", classes)
+        assert min(classes) > 0, classes
+        for opt in (dict(lds_cap=32), dict(lds_cap=32, tiles_per_wave=1), dict(lds_cap=32, tiles_per_wave=3),
+                    dict(lds_cap=32, waves_per_block=2), dict(lds_cap=16)):
+            say("tile stage", name, opt)
+            got = gpu_saif(G, w, wire_transport=not flt, **opt)
+            assert_same(w, got, ref, f"tile stage {name} {opt}")
+            assert got[4]["unstaged_groups"] > 0
+
+
 def test_queue_overflow(G):
     """Inputs with about two toggles in nearly every cycle: single-pin gates
     fed by them have two pin events in most lanes, so their staged tile
