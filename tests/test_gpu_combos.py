@@ -1,0 +1,107 @@
+"""GPU parity over random combinations of the options that change how a run
+is laid out, against the oracle, bit-exact: dead nets released or kept,
+plain, single-lane segment and carried continuous views, windows, staging
+caps, tiles per wave, waves per block, captured-graph rounds and cycle
+sub-ranges, budgets that force windows to shrink and the arena to refill,
+on random designs with every arc feature (wide cells, wires where the view
+allows them).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_06117_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_06117_amd import gatesim
+    return gatesim
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def draw_case(G, case):
+    rng = np.random.default_rng(12_000 + case)
+    view = str(rng.choice(["plain", "plain", "segment", "carry", "carry"]))
+    S = 1 if view == "plain" else int(rng.choice([2, 3, 8, 16, 64]))
+    wide = bool(rng.random() < 0.25)
+    gates = int(rng.integers(30, 800)) if rng.random() < 0.8 else int(rng.integers(800, 4000))
+    C = S * int(rng.integers(2, max(3, 400 // S)))
+    T = int(rng.integers(40, 700))
+    wires = view != "carry" and rng.random() < 0.4
+    w = synth.small_random(12_000 + case, gates, int(rng.integers(16, 40)), min(gates, int(rng.integers(2, 30))),
+                           C, T, float(rng.uniform(0.05, 0.6)), 1, int(rng.integers(2, 90)),
+                           cond_frac=float(rng.choice([0.0, 0.2, 0.5])),
+                           wire=(1, int(rng.integers(1, 30))) if wires else None,
+                           extra=int(rng.choice([0, 0, 2, 4])), extra_p=0.4, skew=min(50, T - 1), wide=wide,
+                           edge_frac=float(rng.choice([0.0, 0.3])))
+    transport = wires and rng.random() < 0.3
+    if transport:
+        w["net_filter"] = False
+    opt = {"release_dead": bool(rng.random() < 0.5), "wire_transport": transport}
+    if rng.random() < 0.5:
+        opt["window_cycles"] = int(rng.choice([37, 64, 100, 256]))
+    if rng.random() < 0.5:
+        opt["tiles_per_wave"] = int(rng.choice([1, 2, 3, 8, 16]))
+    if rng.random() < 0.4:
+        opt["lds_cap"] = int(rng.choice([4, 8, 16, 32]))
+    if rng.random() < 0.3:
+        opt["waves_per_block"] = int(rng.choice([1, 2, 8]))
+        if opt["waves_per_block"] == 8 and opt.get("lds_cap") == 32:
+            opt["waves_per_block"] = 2              # 86 KB of LDS per block may exceed the device's limit
+    if rng.random() < 0.3:
+        opt["schedule"] = G.SCHED_GRAPH
+    if rng.random() < 0.2:
+        # chunk headers and lane ends of the whole run, times 1.3 to 2.5
+        N = w["netlist"]["n_inputs"] + gates
+        opt["hbm_budget"] = int(N * 144 * ((C + 63) // 64) * rng.uniform(1.3, 2.5)) + 65536
+    n = C // S
+    b = int(rng.integers(0, n))
+    e = int(rng.integers(b + 1, n + 1))
+    return w, view, S, wide, opt, b, e
+
+
+@pytest.mark.parametrize("block", range(8))
+def test_option_combinations(G, block):
+    budget_runs = 0
+    for case in range(block * 25, block * 25 + 25):
+        w, view, S, wide, opt, b, e = draw_case(G, case)
+        say("combo", case, view, S, wide, w["stimulus"]["n_cycles"], opt, (b, e))
+        ref = oracle.simulate(w, b, e, segment_cycles=S)
+        try:
+            with G.GateSim(**opt) as sim:
+                if wide:
+                    sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)
+                d, s = sim.load_work(w, cells_loaded=wide)
+                if view == "segment":
+                    s = sim.segment_stimulus(s, S)
+                elif view == "carry":
+                    s = sim.continuous_stimulus(s, S)
+                sim.simulate(d, s, b, e)
+                tc, t0, t1, ig = sim.read_saif_ig(d)
+                st = sim.stats()
+        except G.GateSimError as err:
+            # a budget below what one window needs is refused, never run
+            if "hbm_budget" in opt and err.status == G.GS_E_NOMEM:
+                say("  refused:", err)
+                continue
+            raise
+        if "hbm_budget" in opt:
+            budget_runs += 1
+            say("  windows retried", st["window_retries"])
+        for name, a, r in (("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"]), ("ig", ig, ref["ig"])):
+            if not np.array_equal(a, r):
+                bad = np.nonzero(a != r)[0]
+                raise AssertionError(f"case {case} ({view}, S {S}, {opt}, cycles {b}..{e}): {name} differs on "
+                                     f"{len(bad)} nets, first {bad[:8]} gpu {a[bad[:8]]} oracle {r[bad[:8]]}")
+    say("block", block, "budget runs", budget_runs)
