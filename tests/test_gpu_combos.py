@@ -61,13 +61,19 @@ def draw_case(G, case):
             opt["waves_per_block"] = 2              # 86 KB of LDS per block may exceed the device's limit
     if rng.random() < 0.3:
         opt["schedule"] = G.SCHED_GRAPH
-    if rng.random() < 0.2:
-        # chunk headers and lane ends of the whole run, times 1.3 to 2.5
-        N = w["netlist"]["n_inputs"] + gates
-        opt["hbm_budget"] = int(N * 144 * ((C + 63) // 64) * rng.uniform(1.3, 2.5)) + 65536
     n = C // S
     b = int(rng.integers(0, n))
     e = int(rng.integers(b + 1, n + 1))
+    if rng.random() < 0.2:
+        # The budget holds window headers and arena: 144 B of chunk header and
+        # lane ends per (net, 64-lane tile), a window's headers at most a
+        # third of it.  0.5 to 2.5 times the range's headers splits every
+        # range of more than one tile into windows; the floor leaves one tile
+        # room for dense transitions.
+        N = w["netlist"]["n_inputs"] + gates
+        lanes = (e - b) * (1 if view == "segment" else S)
+        hdr = N * 144 * ((lanes + 63) // 64)
+        opt["hbm_budget"] = max(int(hdr * rng.uniform(0.5, 2.5)), N * 1500 + 65536)
     return w, view, S, wide, opt, b, e
 
 
@@ -98,10 +104,43 @@ def test_option_combinations(G, block):
             raise
         if "hbm_budget" in opt:
             budget_runs += 1
-            say("  windows retried", st["window_retries"])
+            say("  windows", st["windows"], "retried", st["window_retries"])
         for name, a, r in (("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"]), ("ig", ig, ref["ig"])):
             if not np.array_equal(a, r):
                 bad = np.nonzero(a != r)[0]
                 raise AssertionError(f"case {case} ({view}, S {S}, {opt}, cycles {b}..{e}): {name} differs on "
                                      f"{len(bad)} nets, first {bad[:8]} gpu {a[bad[:8]]} oracle {r[bad[:8]]}")
     say("block", block, "budget runs", budget_runs)
+
+
+@pytest.mark.parametrize("block", range(6))
+def test_batch_combinations(G, block):
+    """Batches of two to six jobs drawn like the cases above (each its own
+    design, view and cycle range) under one set of context options: every
+    design's counts equal the oracle's for its job."""
+    for bi in range(block * 5, block * 5 + 5):
+        rng = np.random.default_rng(13_000 + bi)
+        cases = [draw_case(G, 500 + 7 * bi + k) for k in range(int(rng.integers(2, 7)))]
+        opt = {k: v for k, v in cases[0][4].items() if k != "hbm_budget"}
+        opt["wire_transport"] = False
+        jobs_desc = []
+        say("batch", bi, opt, [(c[1], c[2], c[0]["netlist"]["n_gates"], (c[5], c[6])) for c in cases])
+        with G.GateSim(**opt) as sim:
+            sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)     # a superset of every design's library
+            jobs = []
+            for w, view, S, wide, _, b, e in cases:
+                w["net_filter"] = True
+                d, s = sim.load_work(w, cells_loaded=True)
+                if view == "segment":
+                    s = sim.segment_stimulus(s, S)
+                elif view == "carry":
+                    s = sim.continuous_stimulus(s, S)
+                jobs.append((d, s, b, e))
+                jobs_desc.append((d, w, S, b, e))
+            sim.simulate_batch(jobs)
+            for d, w, S, b, e in jobs_desc:
+                tc, t0, t1, ig = sim.read_saif_ig(d)
+                ref = oracle.simulate(w, b, e, segment_cycles=S)
+                for name, a, r in (("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"]),
+                                   ("ig", ig, ref["ig"])):
+                    assert np.array_equal(a, r), f"batch {bi} design {d} (S {S}, cycles {b}..{e}): {name}"
