@@ -519,14 +519,20 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     uint32_t before = 0;                                    // group toggles in earlier tiles
-    uint32_t nact = 0, glitch = 0;
+    uint32_t nact = 0;
+    // the group's share of the input's glitch toggles; on a continuous view
+    // it can be negative (below)
+    int32_t glitch = 0;
     int64_t zt = 0;                                         // final values x T over the lane's cycles
     // Continuous segments of st.seg cycles (the window starts one): a
     // segment's glitch toggles are its toggles less the parity of their
     // number, i.e. less (toggles before its start XOR toggles before its
-    // end) & 1.  The group counts the segments that end in it; pv is that
-    // parity term at the last segment start seen (found by a search when the
-    // segment began before the group).
+    // end) & 1.  The group counts its own toggles and subtracts that term
+    // for the segments that end in it; pv is the parity term at the last
+    // segment start seen (found by a search when the segment began before
+    // the group).  A segment's toggles can all lie in an earlier group, so a
+    // group's share can be negative; the shares of a segment's groups sum to
+    // its count.
     const uint32_t S = st.seg > 1 ? (uint32_t)st.seg : 0u;
     uint32_t pv = 0, odd = 0;
     if (S) {
@@ -567,21 +573,21 @@ __global__ __launch_bounds__(256) void expand_kernel(StimView st, WinView win, S
                 odd += pv ^ pb;
                 pv = pb;
             }
-            glitch += total;
+            glitch += (int32_t)total;
         } else {
-            glitch += total - (uint32_t)__popcll(__ballot(cnt & 1u));   // all but one edge of odd lists
+            glitch += (int32_t)(total - (uint32_t)__popcll(__ballot(cnt & 1u)));   // all but one edge of odd lists
         }
         before += total;
     }
     if (S) {
         if ((uint32_t)c_hi % S == 0u) odd += pv ^ (uint32_t)((gz - lo) & 1);   // a segment ends with the group
-        glitch -= odd;
+        glitch -= (int32_t)odd;
     }
     const int64_t sum1 = wave_sum64(zt + s1);
     if (lane == 0) {
         __hip_atomic_fetch_add(glob(acc.tc + i), (unsigned long long)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (glitch)
-            __hip_atomic_fetch_add(glob(acc.ig + i), (unsigned long long)glitch, __ATOMIC_RELAXED,
+        if (glitch)                                         // sign-extended: a negative share subtracts
+            __hip_atomic_fetch_add(glob(acc.ig + i), (unsigned long long)(int64_t)glitch, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(glob(acc.t1 + i), (unsigned long long)sum1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

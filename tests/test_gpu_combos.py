@@ -144,3 +144,32 @@ def test_batch_combinations(G, block):
                 for name, a, r in (("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"]),
                                    ("ig", ig, ref["ig"])):
                     assert np.array_equal(a, r), f"batch {bi} design {d} (S {S}, cycles {b}..{e}): {name}"
+
+
+@pytest.mark.parametrize("block", range(3))
+def test_noalloc_combinations(G, block):
+    """The allocation-free entry point on cases drawn like the ones above
+    (its scratch sets the window memory, and it keeps every net), called
+    twice in a row on one context with other calls between: the oracle's
+    counts each time."""
+    for case in range(800 + block * 20, 800 + block * 20 + 20):
+        w, view, S, wide, opt, b, e = draw_case(G, case)
+        opt.pop("hbm_budget", None)
+        say("noalloc combo", case, view, S, wide, w["stimulus"]["n_cycles"], opt, (b, e))
+        ref = oracle.simulate(w, b, e, segment_cycles=S)
+        want = (ref["tc"], ref["t0"], ref["t1"], ref["ig"])
+        with G.GateSim(**opt) as sim:
+            if wide:
+                sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)
+            d, s = sim.load_work(w, cells_loaded=wide)
+            if view == "segment":
+                s = sim.segment_stimulus(s, S)
+            elif view == "carry":
+                s = sim.continuous_stimulus(s, S)
+            for rep in range(2):
+                sim.simulate_noalloc(d, s, b, e)
+                got = sim.read_saif_ig(d, reset=True)
+                for name, a, r in zip(("tc", "t0", "t1", "ig"), got, want):
+                    assert np.array_equal(a, r), f"case {case} ({view}, S {S}, {opt}, cycles {b}..{e}) call {rep}: {name}"
+                sim.simulate(d, s, b, min(e, b + 1))         # a regular call between
+                sim.read_saif_ig(d, reset=True)

@@ -90,6 +90,30 @@ def test_carry_matches_oracle(G, S):
         assert not np.array_equal(iso["t1"], ref["t1"])    # the segments do cross cycle boundaries
 
 
+def test_carry_input_glitches_across_expansion_groups(G):
+    """Regression: the stimulus expansion counts an input's glitch toggles
+    per group of four 64-cycle tiles, and a segment can end in a group that
+    holds none of its toggles (S = 3, segment 85 = cycles 255-257 straddles
+    the groups at cycle 256, and the last group, cycles 256-260, is short).
+    That group's share is negative and must subtract.  Input 0 toggles once
+    in that segment (IG 0), input 1 twice in segment 33 and once in segment
+    85 (IG 2), input 2 twice before cycle 256 and once after it, all in
+    segment 85 (IG 2); input 3 toggles every seventh cycle."""
+    from tests.handmade import work
+    T, C, S = 100, 261, 3
+    tog = [[255 * T + 50],
+           [100 * T + 30, 101 * T + 60, 255 * T + 40],
+           [255 * T + 10, 255 * T + 60, 256 * T + 20],
+           [c * T + 35 for c in range(0, C, 7)]]
+    w = work(4, [("BUF", [i]) for i in range(4)], (5, 5), tog, [0, 1, 0, 1], period=T, n_cycles=C)
+    ref = oracle.simulate(w, segment_cycles=S)
+    assert ref["ig"][:3].tolist() == [0, 2, 2]
+    for opt in (dict(), dict(noalloc=True), dict(tiles_per_wave=1)):
+        say("carry input glitches", opt)
+        assert_same(run_view(G, w, S, **opt), ref, f"input glitches {opt}")
+    assert_same(run_view(G, w, S, 1, C // S), oracle.simulate(w, 1, C // S, segment_cycles=S), "from segment 1")
+
+
 @pytest.mark.parametrize("S", [16, 50])
 def test_carry_wide_cells(G, S):
     """Cells of four to six pins (delays read per pin, not from the table)."""
