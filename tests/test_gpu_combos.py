@@ -4,7 +4,8 @@ plain, single-lane segment and carried continuous views, windows, staging
 caps, tiles per wave, waves per block, captured-graph rounds and cycle
 sub-ranges, budgets that force windows to shrink and the arena to refill,
 on random designs with every arc feature (wide cells, wires where the view
-allows them).
+allows them); the same for batches, for the allocation-free entry point and
+for serving (window and delay-edit requests from several threads).
 """
 import sys
 
@@ -173,3 +174,91 @@ def test_noalloc_combinations(G, block):
                     assert np.array_equal(a, r), f"case {case} ({view}, S {S}, {opt}, cycles {b}..{e}) call {rep}: {name}"
                 sim.simulate(d, s, b, min(e, b + 1))         # a regular call between
                 sim.read_saif_ig(d, reset=True)
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_serve_combinations(G, block):
+    """Serving under random context options (tiles per wave, caps, block
+    shapes, transport wires): two or three resident designs with every arc
+    feature, on plain or single-lane segment views, and sixteen window and
+    delay-edit requests submitted from three threads; every result equals
+    the oracle's for its range (an edit's: the resident range with the
+    edited arcs)."""
+    import threading
+    from tests.test_gpu_serve import edited_arcs, random_edits
+    for ci in range(block * 2, block * 2 + 2):
+        rng = np.random.default_rng(14_000 + ci)
+        opt = {"wire_transport": bool(rng.random() < 0.3)}
+        if rng.random() < 0.5:
+            opt["tiles_per_wave"] = int(rng.choice([1, 2, 4, 8]))
+        if rng.random() < 0.4:
+            opt["lds_cap"] = int(rng.choice([4, 8, 16, 32]))
+        if rng.random() < 0.3:
+            opt["waves_per_block"] = int(rng.choice([1, 2, 8]))
+            if opt["waves_per_block"] == 8 and opt.get("lds_cap") == 32:
+                opt["waves_per_block"] = 2
+        designs = []
+        for k in range(int(rng.integers(2, 4))):
+            S = int(rng.choice([1, 1, 1, 3, 8]))
+            n_view = int(rng.integers(20, 200 // S + 21))
+            T = int(rng.integers(60, 700))
+            gates = int(rng.integers(50, 1500))
+            wires = rng.random() < 0.4
+            w = synth.small_random(14_000 + 10 * ci + k, gates, int(rng.integers(16, 40)),
+                                   min(gates, int(rng.integers(2, 30))), S * n_view, T, float(rng.uniform(0.05, 0.5)),
+                                   1, int(rng.integers(2, 90)), cond_frac=float(rng.choice([0.0, 0.2])),
+                                   wire=(1, int(rng.integers(1, 30))) if wires else None,
+                                   extra=int(rng.choice([0, 2])), extra_p=0.4, skew=min(50, T - 1),
+                                   wide=bool(rng.random() < 0.3), edge_frac=float(rng.choice([0.0, 0.3])))
+            w["net_filter"] = not (wires and opt["wire_transport"])
+            rb = int(rng.integers(0, n_view - 1))
+            designs.append((w, S, n_view, rb, int(rng.integers(1, n_view - rb + 1))))
+        say("serve combo", ci, opt, [(d[0]["netlist"]["n_gates"], d[1], d[2], d[3], d[4]) for d in designs])
+        plan = []
+        for r in range(16):
+            k = int(rng.integers(len(designs)))
+            w, S, n_view, rb, rn = designs[k]
+            if rng.random() < 0.5:
+                b = int(rng.integers(0, n_view))
+                plan.append(("w", k, (b, int(rng.integers(b + 1, n_view + 1)))))
+            else:
+                plan.append(("e", k, random_edits(rng, w, int(rng.integers(1, 12)))))
+        sim = G.GateSim(**opt)
+        started = False
+        try:
+            sim.load_cells(synth.WIDE_PINS, synth.WIDE_TRUTH)            # a superset of every design's library
+            ids = []
+            for w, S, n_view, rb, rn in designs:
+                d, s = sim.load_work(w, cells_loaded=True)
+                ids.append((d, sim.segment_stimulus(s, S) if S > 1 else s))
+            sim.serve_start([(d, v, designs[k][3], designs[k][4]) for k, (d, v) in enumerate(ids)], max_queue=256)
+            started = True
+            tickets = [None] * len(plan)
+
+            def worker(lo):
+                for j in range(lo, len(plan), 3):
+                    kind, k, arg = plan[j]
+                    tickets[j] = (sim.submit_window(*ids[k], *arg) if kind == "w" else
+                                  sim.submit_edit(*ids[k], arg))
+
+            ths = [threading.Thread(target=worker, args=(lo,)) for lo in range(3)]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+            for j, t in enumerate(tickets):
+                r = sim.poll(t, wait=True)
+                sim.release(t)
+                assert r["status"] == 0, r.get("error")
+                kind, k, arg = plan[j]
+                w, S, n_view, rb, rn = designs[k]
+                if kind == "w":
+                    ref = oracle.simulate(w, arg[0], arg[1], segment_cycles=S)
+                else:
+                    ref = oracle.simulate(dict(w, arcs=edited_arcs(w["arcs"], arg)), rb, rb + rn, segment_cycles=S)
+                for name in ("tc", "t0", "t1", "ig"):
+                    assert np.array_equal(r[name], ref[name]), f"serve case {ci} request {j} ({kind}, design {k}): {name}"
+        finally:
+            if started:
+                sim.serve_stop()
+            sim.close()
