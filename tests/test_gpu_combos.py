@@ -4,8 +4,9 @@ plain, single-lane segment and carried continuous views, windows, staging
 caps, tiles per wave, waves per block, captured-graph rounds and cycle
 sub-ranges, budgets that force windows to shrink and the arena to refill,
 on random designs with every arc feature (wide cells, wires where the view
-allows them); the same for batches, for the allocation-free entry point and
-for serving (window and delay-edit requests from several threads).
+allows them), with sampled waveforms read back where the range runs as one
+window; the same for batches, for the allocation-free entry point and for
+serving (window and delay-edit requests from several threads).
 """
 import sys
 
@@ -84,7 +85,14 @@ def test_option_combinations(G, block):
     for case in range(block * 25, block * 25 + 25):
         w, view, S, wide, opt, b, e = draw_case(G, case)
         say("combo", case, view, S, wide, w["stimulus"]["n_cycles"], opt, (b, e))
-        ref = oracle.simulate(w, b, e, segment_cycles=S)
+        # the waveforms stay readable when the range runs as one window
+        # (ranges here are shorter than the default window) and every net is kept
+        readable = not (opt["release_dead"] or "window_cycles" in opt or "hbm_budget" in opt)
+        rng = np.random.default_rng(case)
+        N = w["netlist"]["n_inputs"] + w["netlist"]["n_gates"]
+        probes = ([(int(n), int(k)) for n, k in zip(rng.integers(0, N, 40), rng.integers(b, e, 40))]
+                  if readable else [])
+        ref = oracle.simulate(w, b, e, probes=probes, segment_cycles=S)
         try:
             with G.GateSim(**opt) as sim:
                 if wide:
@@ -97,6 +105,7 @@ def test_option_combinations(G, block):
                 sim.simulate(d, s, b, e)
                 tc, t0, t1, ig = sim.read_saif_ig(d)
                 st = sim.stats()
+                waves = [sim.read_waveform(d, s, n, k) for n, k in probes]
         except G.GateSimError as err:
             # a budget below what one window needs is refused, never run
             if "hbm_budget" in opt and err.status == G.GS_E_NOMEM:
@@ -111,6 +120,8 @@ def test_option_combinations(G, block):
                 bad = np.nonzero(a != r)[0]
                 raise AssertionError(f"case {case} ({view}, S {S}, {opt}, cycles {b}..{e}): {name} differs on "
                                      f"{len(bad)} nets, first {bad[:8]} gpu {a[bad[:8]]} oracle {r[bad[:8]]}")
+        for (n, k), gw, ow in zip(probes, waves, ref["probes"]):
+            assert gw == ow, f"case {case} ({view}, S {S}, {opt}): waveform of net {n} in cycle {k}"
     say("block", block, "budget runs", budget_runs)
 
 
