@@ -32,12 +32,14 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def draw_case(G, case):
+def draw_case(G, case, dense=False):
     rng = np.random.default_rng(12_000 + case)
     view = str(rng.choice(["plain", "plain", "segment", "carry", "carry"]))
     S = 1 if view == "plain" else int(rng.choice([2, 3, 8, 16, 64]))
     wide = bool(rng.random() < 0.25)
     gates = int(rng.integers(30, 800)) if rng.random() < 0.8 else int(rng.integers(800, 4000))
+    if dense:
+        gates = int(rng.integers(30, 500))
     C = S * int(rng.integers(2, max(3, 400 // S)))
     T = int(rng.integers(40, 700))
     wires = view != "carry" and rng.random() < 0.4
@@ -45,7 +47,8 @@ def draw_case(G, case):
                            C, T, float(rng.uniform(0.05, 0.6)), 1, int(rng.integers(2, 90)),
                            cond_frac=float(rng.choice([0.0, 0.2, 0.5])),
                            wire=(1, int(rng.integers(1, 30))) if wires else None,
-                           extra=int(rng.choice([0, 0, 2, 4])), extra_p=0.4, skew=min(50, T - 1), wide=wide,
+                           extra=int(rng.choice([5, 6])) if dense else int(rng.choice([0, 0, 2, 4])),
+                           extra_p=0.9 if dense else 0.4, skew=min(50, T - 1), wide=wide,
                            edge_frac=float(rng.choice([0.0, 0.3])))
     transport = wires and rng.random() < 0.3
     if transport:
@@ -79,11 +82,15 @@ def draw_case(G, case):
     return w, view, S, wide, opt, b, e
 
 
-@pytest.mark.parametrize("block", range(8))
+@pytest.mark.parametrize("block", range(10))
 def test_option_combinations(G, block):
+    """Blocks 8 and 9 draw dense inputs (five or six extra toggles per cycle
+    on most inputs), so that tile groups outgrow the fanin stage, lanes
+    outgrow their output slots and queues overflow."""
     budget_runs = 0
+    dense = block >= 8
     for case in range(block * 25, block * 25 + 25):
-        w, view, S, wide, opt, b, e = draw_case(G, case)
+        w, view, S, wide, opt, b, e = draw_case(G, case, dense=dense)
         say("combo", case, view, S, wide, w["stimulus"]["n_cycles"], opt, (b, e))
         # the waveforms stay readable when the range runs as one window
         # (ranges here are shorter than the default window) and every net is kept
@@ -115,6 +122,9 @@ def test_option_combinations(G, block):
         if "hbm_budget" in opt:
             budget_runs += 1
             say("  windows", st["windows"], "retried", st["window_retries"])
+        if dense:
+            say("  unstaged groups", st["unstaged_groups"], "spilled lanes", st["spilled_lanes"],
+                "queue overflows", st["queue_overflows"])
         for name, a, r in (("tc", tc, ref["tc"]), ("t0", t0, ref["t0"]), ("t1", t1, ref["t1"]), ("ig", ig, ref["ig"])):
             if not np.array_equal(a, r):
                 bad = np.nonzero(a != r)[0]
