@@ -318,6 +318,27 @@ def test_continuous_segments():
         oracle.simulate(w, segment_cycles=3)
 
 
+def test_segment_input_glitches():
+    """An input's glitch toggles in a continuous segment are its toggles in
+    the segment less one when their number is odd (the net's value then
+    changes across the segment).  Three-cycle segments of 100 ps: one toggle
+    in a segment gives none, two give two, three give two, and toggles in
+    different segments never pair; cycle by cycle the same toggles pair
+    only within a cycle."""
+    T = 100
+    tog = [[255 * T + 50],                                      # segment 85: 1 toggle
+           [100 * T + 30, 101 * T + 60, 255 * T + 40],          # segment 33: 2, segment 85: 1
+           [255 * T + 10, 255 * T + 60, 256 * T + 20],          # segment 85: 3 (2 in cycle 255)
+           [c * T + 35 for c in range(0, 261, 7)],              # one per segment at most
+           [3 * T + 10, 3 * T + 20, 5 * T + 90]]                # segment 1: 3 (2 in cycle 3)
+    w = work(5, [("BUF", [i]) for i in range(5)], (5, 5), tog, [0, 1, 0, 1, 0], period=T, n_cycles=261)
+    seg = oracle.simulate(w, segment_cycles=3)
+    assert seg["ig"][:5].tolist() == [0, 2, 2, 0, 2]
+    assert seg["tc"][:5].tolist() == [1, 3, 3, 38, 3]
+    iso = oracle.simulate(w)
+    assert iso["ig"][:5].tolist() == [0, 0, 2, 0, 2]
+
+
 def test_late_lanes():
     """A cycle ends quiescent unless a net's last edge, or its arrival at a
     fanout pin through the pin's wire, reaches the period."""
