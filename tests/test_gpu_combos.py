@@ -32,7 +32,7 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def draw_case(G, case, dense=False):
+def draw_case(G, case, dense=False, extreme=False):
     rng = np.random.default_rng(12_000 + case)
     view = str(rng.choice(["plain", "plain", "segment", "carry", "carry"]))
     S = 1 if view == "plain" else int(rng.choice([2, 3, 8, 16, 64]))
@@ -42,6 +42,10 @@ def draw_case(G, case, dense=False):
         gates = int(rng.integers(30, 500))
     C = S * int(rng.integers(2, max(3, 400 // S)))
     T = int(rng.integers(40, 700))
+    if extreme:
+        # periods far below the arc delays (every edge lands cycles later)
+        # or near the largest period a segment may span (2^24 ps)
+        T = int(rng.choice([1, 2, 5, 17, (1 << 24) // S - int(rng.integers(0, 1000))]))
     wires = view != "carry" and rng.random() < 0.4
     w = synth.small_random(12_000 + case, gates, int(rng.integers(16, 40)), min(gates, int(rng.integers(2, 30))),
                            C, T, float(rng.uniform(0.05, 0.6)), 1, int(rng.integers(2, 90)),
@@ -82,15 +86,16 @@ def draw_case(G, case, dense=False):
     return w, view, S, wide, opt, b, e
 
 
-@pytest.mark.parametrize("block", range(10))
+@pytest.mark.parametrize("block", range(12))
 def test_option_combinations(G, block):
     """Blocks 8 and 9 draw dense inputs (five or six extra toggles per cycle
     on most inputs), so that tile groups outgrow the fanin stage, lanes
-    outgrow their output slots and queues overflow."""
+    outgrow their output slots and queues overflow; blocks 10 and 11 draw
+    periods of 1 to 17 ps or near 2^24 ps per segment."""
     budget_runs = 0
-    dense = block >= 8
+    dense = block in (8, 9)
     for case in range(block * 25, block * 25 + 25):
-        w, view, S, wide, opt, b, e = draw_case(G, case, dense=dense)
+        w, view, S, wide, opt, b, e = draw_case(G, case, dense=dense, extreme=block >= 10)
         say("combo", case, view, S, wide, w["stimulus"]["n_cycles"], opt, (b, e))
         # the waveforms stay readable when the range runs as one window
         # (ranges here are shorter than the default window) and every net is kept
