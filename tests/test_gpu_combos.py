@@ -140,14 +140,16 @@ def test_option_combinations(G, block):
     say("block", block, "budget runs", budget_runs)
 
 
-@pytest.mark.parametrize("block", range(6))
+@pytest.mark.parametrize("block", range(8))
 def test_batch_combinations(G, block):
     """Batches of two to six jobs drawn like the cases above (each its own
     design, view and cycle range) under one set of context options: every
-    design's counts equal the oracle's for its job."""
+    design's counts equal the oracle's for its job.  Block 6 draws dense
+    inputs, block 7 extreme periods."""
     for bi in range(block * 5, block * 5 + 5):
         rng = np.random.default_rng(13_000 + bi)
-        cases = [draw_case(G, 500 + 7 * bi + k) for k in range(int(rng.integers(2, 7)))]
+        cases = [draw_case(G, 500 + 7 * bi + k, dense=block == 6, extreme=block == 7)
+                 for k in range(int(rng.integers(2, 7)))]
         opt = {k: v for k, v in cases[0][4].items() if k != "hbm_budget"}
         opt["wire_transport"] = False
         jobs_desc = []
@@ -173,14 +175,14 @@ def test_batch_combinations(G, block):
                     assert np.array_equal(a, r), f"batch {bi} design {d} (S {S}, cycles {b}..{e}): {name}"
 
 
-@pytest.mark.parametrize("block", range(3))
+@pytest.mark.parametrize("block", range(5))
 def test_noalloc_combinations(G, block):
     """The allocation-free entry point on cases drawn like the ones above
     (its scratch sets the window memory, and it keeps every net), called
     twice in a row on one context with other calls between: the oracle's
-    counts each time."""
+    counts each time.  Block 3 draws dense inputs, block 4 extreme periods."""
     for case in range(800 + block * 20, 800 + block * 20 + 20):
-        w, view, S, wide, opt, b, e = draw_case(G, case)
+        w, view, S, wide, opt, b, e = draw_case(G, case, dense=block == 3, extreme=block == 4)
         opt.pop("hbm_budget", None)
         say("noalloc combo", case, view, S, wide, w["stimulus"]["n_cycles"], opt, (b, e))
         ref = oracle.simulate(w, b, e, segment_cycles=S)
