@@ -88,10 +88,10 @@ typedef struct {
     int32_t  window_cycles;   /* cycles per window; 0 = as many as fit the budget, capped at 16384 */
     int32_t  lds_cap;         /* transitions per (net, cycle) staged on chip by the per-tile walk (tile groups
                                  too large for the on-chip stage, cells of four or more pins, overflowing
-                                 queues) before its spill path: 4, 8, 16 or 32;
+                                 queues) before its spill path: 4, 8, 16, 24 or 32;
                                  0 = chosen per round from the input toggles per (input, cycle), or the
                                  transitions per (net, cycle) the design showed in its last round if higher:
-                                 8 up to 0.5, 16 up to 1, else 32 (segment views carry many cycles per lane,
+                                 8 up to 0.5, 16 up to 1, 24 up to 3, else 32 (segment views carry many cycles per lane,
                                  glitch-heavy logic multiplies its inputs' toggles); serving uses 8 */
     int32_t  waves_per_block; /* 1, 2, 4 or 8; 0 = 4 */
     int32_t  schedule;        /* GS_SCHED_LEVELS or GS_SCHED_GRAPH */

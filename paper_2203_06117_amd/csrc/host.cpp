@@ -244,8 +244,8 @@ extern "C" gs_status gs_create(const gs_options *opt, gs_ctx **out)
     if (o.waves_per_block == 0) o.waves_per_block = 4;
     if (o.tiles_per_wave == 0) o.tiles_per_wave = 8;
     if (o.tiles_per_wave < 1 || o.tiles_per_wave > 64) return gs_fail(nullptr, GS_E_INVALID, "tiles_per_wave must be 1..64");
-    if (o.lds_cap != 4 && o.lds_cap != 8 && o.lds_cap != 16 && o.lds_cap != 32)
-        return gs_fail(nullptr, GS_E_INVALID, "lds_cap must be 4, 8, 16 or 32");
+    if (o.lds_cap != 4 && o.lds_cap != 8 && o.lds_cap != 16 && o.lds_cap != 24 && o.lds_cap != 32)
+        return gs_fail(nullptr, GS_E_INVALID, "lds_cap must be 4, 8, 16, 24 or 32");
     if (o.waves_per_block < 1 || o.waves_per_block > 8) return gs_fail(nullptr, GS_E_INVALID, "waves_per_block must be 1..8");
     if (o.schedule != GS_SCHED_LEVELS && o.schedule != GS_SCHED_GRAPH) return gs_fail(nullptr, GS_E_INVALID, "bad schedule");
     if (o.window_cycles < 0) return gs_fail(nullptr, GS_E_INVALID, "negative window");

@@ -1790,6 +1790,7 @@ static hipError_t launch_ge(const Seg *segs, int32_t n_segs, uint64_t n_waves, i
     case 8: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 8, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
     case 16: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 16, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
     case 32: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 32, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
+    case 24: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 24, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
     case 4: hipLaunchKernelGGL((gate_eval_kernel<WIRES, 4, KMAX, REMAP, CONT>), grid, block, lds, s, segs, n_segs, n_waves, tpw); break;
     default: return hipErrorInvalidValue;
     }

@@ -74,7 +74,7 @@ Tuning tuning_for(const gs_ctx *ctx, const std::vector<Piece> &ps)
         rho = std::max(rho, (double)tog / ((double)std::max(1, p.d->I) * std::max(1, p.cycles)));
         rho = std::max(rho, p.d->words_per_ps * (double)p.s->period);
     }
-    t.cap = rho <= 0.5 ? 8 : rho <= 1.0 ? 16 : 32;
+    t.cap = rho <= 0.5 ? 8 : rho <= 1.0 ? 16 : rho <= 3.0 ? 24 : 32;
     while (t.wpb > 1 && gate_eval_lds_bytes(t.cap, t.wpb) > ctx->lds_limit) t.wpb /= 2;   // fit the block's LDS
     return carry_tuning(t, ps);
 }

@@ -322,6 +322,26 @@ def test_dense_activity(G):
             assert got[4]["spilled_lanes"] > 0
 
 
+def test_cap_24_spills(G):
+    """The cap the library picks for glitch-heavy rounds (24 staged edges per
+    lane): inputs with about thirteen toggles per cycle give gate outputs up
+    to 39 edges in a cycle (512 (net, cycle) lists above 24, from the
+    oracle's probes), so lanes take the spill path; every tile and block
+    shape must match the oracle."""
+    w = synth.small_random(83, 300, 16, 8, 128, 2000, 0.9, 2, 30, cond_frac=0.2, extra=12, extra_p=1.0,
+                           edge_frac=0.3)
+    probes = [(n, c) for n in range(16, 316) for c in range(128)]
+    ref = oracle.simulate(w, probes=probes)
+    ln = np.array([p[2] for p in ref["probes"]])
+    assert (ln > 24).sum() > 0, ln.max()
+    for opt in (dict(lds_cap=24), dict(lds_cap=24, tiles_per_wave=1), dict(lds_cap=24, tiles_per_wave=3),
+                dict(lds_cap=24, waves_per_block=8), dict(lds_cap=24, window_cycles=64)):
+        say("cap 24", opt)
+        got = gpu_saif(G, w, **opt)
+        assert_same(w, got, ref, f"cap 24 {opt}")
+        assert got[4]["spilled_lanes"] > 0
+
+
 def tile_fanin_words(w, ref_probes, n_nets, n_cycles):
     """Fanin words of every (gate, 64-cycle tile): the transitions of its pin
     nets over the tile, from the oracle's probe lengths."""
