@@ -63,7 +63,7 @@ def draw_case(G, case, dense=False, extreme=False):
     if rng.random() < 0.5:
         opt["tiles_per_wave"] = int(rng.choice([1, 2, 3, 8, 16]))
     if rng.random() < 0.4:
-        opt["lds_cap"] = int(rng.choice([4, 8, 16, 32]))
+        opt["lds_cap"] = int(rng.choice([4, 8, 16, 24, 32]))
     if rng.random() < 0.3:
         opt["waves_per_block"] = int(rng.choice([1, 2, 8]))
         if opt["waves_per_block"] == 8 and opt.get("lds_cap") == 32:
@@ -220,7 +220,7 @@ def test_serve_combinations(G, block):
         if rng.random() < 0.5:
             opt["tiles_per_wave"] = int(rng.choice([1, 2, 4, 8]))
         if rng.random() < 0.4:
-            opt["lds_cap"] = int(rng.choice([4, 8, 16, 32]))
+            opt["lds_cap"] = int(rng.choice([4, 8, 16, 24, 32]))
         if rng.random() < 0.3:
             opt["waves_per_block"] = int(rng.choice([1, 2, 8]))
             if opt["waves_per_block"] == 8 and opt.get("lds_cap") == 32:
